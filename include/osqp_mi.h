@@ -1,0 +1,193 @@
+/*
+ * osqp_mi -- MI355X (gfx950) implementation of the operator-splitting QP
+ * method of Stellato, Banjac, Goulart, Bemporad and Boyd, "OSQP: An Operator
+ * Splitting Solver for Quadratic Programs".
+ *
+ *   minimize   1/2 x'Px + q'x
+ *   subject to l <= Ax <= u                                   (Section 1, eq. pb:qp)
+ *
+ * C ABI.  Every input pointer is host memory, borrowed for the duration of
+ * the call only (the library copies what it needs).  Outputs go to caller
+ * buffers.  Every function returns 0 on success or one of the OSQP_ERR_*
+ * codes below; no C++ exception crosses this boundary.  A handle is used by
+ * one host thread at a time; all device work of a handle runs on the stream
+ * given in the settings (NULL: the library's own stream).
+ */
+#ifndef OSQP_MI_H
+#define OSQP_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t osqp_int;
+typedef double osqp_float;
+
+/* ---- error codes (returned by every function) ------------------------- */
+#define OSQP_OK 0
+#define OSQP_ERR_DIM 1            /* n <= 0, m < 0, sizes disagree          */
+#define OSQP_ERR_CSR 2            /* bad indptr/indices (range, order)      */
+#define OSQP_ERR_P_NOT_UPPER 3    /* P holds an entry below the diagonal    */
+#define OSQP_ERR_DATA_NONFINITE 4 /* NaN/inf in P, A or q; NaN in l or u    */
+#define OSQP_ERR_L_GT_U 5         /* some l_i > u_i                          */
+#define OSQP_ERR_SETTINGS 6       /* sigma<=0, rho<=0, alpha not in (0,2), eps<0, ... */
+#define OSQP_ERR_ALLOC 7          /* device or host allocation failed       */
+#define OSQP_ERR_BUDGET 8         /* request larger than the server's HBM budget */
+#define OSQP_ERR_DEVICE 9         /* a HIP call failed                      */
+#define OSQP_ERR_NOT_SETUP 10     /* NULL handle or missing data            */
+#define OSQP_ERR_INDEX 11         /* problem index / ticket out of range    */
+#define OSQP_ERR_NO_DEVICE 12     /* no HIP device visible                   */
+
+/* ---- solve status (info.status), Sections 3.3-3.4 --------------------- */
+#define OSQP_SOLVED 1
+#define OSQP_PRIMAL_INFEASIBLE 2  /* y holds the certificate c^-1 E dy (Section 5.1) */
+#define OSQP_DUAL_INFEASIBLE 3    /* x holds the certificate D dx (Section 5.1)      */
+#define OSQP_MAX_ITER_REACHED 4
+#define OSQP_TIME_LIMIT_REACHED 5
+#define OSQP_UNSOLVED 6
+
+/* ---- settings enums ----------------------------------------------------- */
+#define OSQP_PRECISION_FP64 0       /* every step in double                  */
+#define OSQP_PRECISION_FP32_MIXED 1 /* SpMV/PCG/updates in float; scaling,
+                                       checks, certificates, polish in double */
+#define OSQP_LINSYS_AUTO 0          /* dense factor for tiny QPs, else PCG    */
+#define OSQP_LINSYS_PCG 1           /* reduced system, Section 3.1 indirect   */
+#define OSQP_LINSYS_DENSE 2         /* dense Cholesky of the reduced matrix   */
+
+/* Compressed sparse rows.  indptr has nrows+1 entries, indptr[0] = 0,
+ * non-decreasing, indptr[nrows] = nnz; each row's column indices strictly
+ * increase and lie in [0, ncols). */
+typedef struct {
+  osqp_int nrows, ncols, nnz;
+  const osqp_int *indptr;
+  const osqp_int *indices;
+  const osqp_float *data;
+} osqp_csr;
+
+/* One QP: P is the upper triangle of the symmetric cost matrix (diagonal
+ * included), n x n; A is m x n.  Bounds: IEEE inf or |b| >= 1e30 mean
+ * "no bound" (Section 1: l_i in {-inf} u R, u_i in R u {+inf}). */
+typedef struct {
+  osqp_int n, m;
+  osqp_csr P_upper;
+  const osqp_float *q;   /* n */
+  osqp_csr A;
+  const osqp_float *l;   /* m */
+  const osqp_float *u;   /* m */
+} osqp_problem;
+
+typedef struct {
+  osqp_float rho;          /* rho-bar^0 (Section 5.2), default 0.1          */
+  osqp_float sigma;        /* Section 5.2, default 1e-6                      */
+  osqp_float alpha;        /* relaxation, (0,2), default 1.6                  */
+  osqp_float eps_abs, eps_rel;            /* Section 3.4, default 1e-3       */
+  osqp_float eps_prim_inf, eps_dual_inf;  /* Section 3.4, default 1e-4       */
+  osqp_float delta;        /* polish regularisation (Section 4), 1e-6        */
+  osqp_float time_limit;   /* seconds of solve time, 0 = none                */
+  osqp_float pcg_tol_frac; /* inner PCG tolerance factor, default 0.15        */
+  osqp_int max_iter;       /* default 4000                                   */
+  osqp_int check_every;    /* termination-check interval, default 25         */
+  osqp_int scaling_iters;  /* Ruiz passes (Section 5.1), default 10          */
+  osqp_int adaptive_rho;   /* Section 5.2 rho-bar rule, default 1            */
+  osqp_int polish;         /* Section 4, default 0                           */
+  osqp_int polish_refine_iter; /* iterative-refinement passes, default 3     */
+  osqp_int precision;      /* OSQP_PRECISION_*, default FP32_MIXED          */
+  osqp_int linsys;         /* OSQP_LINSYS_*, default AUTO                    */
+  osqp_int pcg_max_iter;   /* PCG iterations per ADMM step, default 50       */
+  osqp_int block_size;     /* threads per workgroup, 0 = autotuned           */
+  void *stream;            /* hipStream_t to run on, NULL = own stream       */
+} osqp_settings;
+
+typedef struct {
+  osqp_int status;         /* OSQP_SOLVED, ...                               */
+  osqp_int iter;           /* ADMM iterations                                */
+  osqp_int pcg_iter;       /* total inner PCG iterations                     */
+  osqp_int rho_updates;
+  osqp_int polish_status;  /* 1 accepted, -1 rejected, 0 not run            */
+  osqp_float obj_val;      /* 1/2 x'Px + q'x on the original data (FP64)    */
+  osqp_float prim_res, dual_res, eps_prim, eps_dual; /* unscaled, FP64, Sections 3.4/5.1 */
+  osqp_float rho_bar;      /* final rho-bar                                  */
+  osqp_float setup_time, solve_time, polish_time;   /* seconds              */
+} osqp_info;
+
+typedef struct osqp_batch osqp_batch;
+typedef struct osqp_batch osqp_solver;   /* a single QP is a batch of one */
+typedef struct osqp_server osqp_server;
+
+/* Fill *s with the defaults listed above (Section 7 defaults where the paper
+ * gives them).  Returns OSQP_ERR_NOT_SETUP if s is NULL. */
+osqp_int osqp_set_default_settings(osqp_settings *s);
+
+/* Human-readable name of an error code (static storage). */
+const char *osqp_error_string(osqp_int code);
+
+/* Number of visible HIP devices (0 when none), for callers that must gate. */
+osqp_int osqp_device_count(void);
+
+/* ---- single QP (Sections 3-5) ------------------------------------------ */
+
+/* Validate and copy one QP to the device, build P's full symmetric pattern
+ * and the rows of A' (= the columns of A), run the modified Ruiz
+ * equilibration of Section 5.1 on the device and set the rho vector of
+ * Section 5.2.  s may be NULL (defaults).  On error *out is NULL. */
+osqp_int osqp_setup(osqp_solver **out, osqp_int n, osqp_int m,
+                    const osqp_csr *P_upper, const osqp_float *q,
+                    const osqp_csr *A, const osqp_float *l, const osqp_float *u,
+                    const osqp_settings *s);
+
+/* Run ADMM (Algorithm 1, reduced-system PCG form of Section 3.1) until a
+ * status of Sections 3.3-3.4 is reached, then unscale (Section 5.1) and,
+ * if enabled, polish (Section 4).  Blocks until the result is on the host. */
+osqp_int osqp_solve(osqp_solver *h);
+
+/* Replace q, l and/or u (NULL = unchanged), unscaled, same sizes
+ * (Section 6, vectors as parameters): the stored scaling D, E, c is applied
+ * and the matrices stay resident.  Rows whose l_i == u_i status changes get
+ * their rho_i updated. */
+osqp_int osqp_update_vectors(osqp_solver *h, const osqp_float *q,
+                             const osqp_float *l, const osqp_float *u);
+
+/* Warm start (Section 6): x0 = x, y0 = y (unscaled; NULL = keep the
+ * current iterate), z0 = A x0. */
+osqp_int osqp_warm_start(osqp_solver *h, const osqp_float *x, const osqp_float *y);
+
+/* Copy the last solution (unscaled, FP64) to x (n) and y (m); either may be NULL. */
+osqp_int osqp_get_solution(const osqp_solver *h, osqp_float *x, osqp_float *y);
+osqp_int osqp_get_info(const osqp_solver *h, osqp_info *info);
+void osqp_cleanup(osqp_solver *h);
+
+/* ---- batches of independent QPs (same settings) ----------------------- */
+
+/* Set up `count` QPs at once; they are packed block-diagonally in HBM and
+ * solved together by one persistent kernel. */
+osqp_int osqp_batch_setup(osqp_batch **out, osqp_int count, const osqp_problem *probs,
+                          const osqp_settings *s);
+/* Solve every QP of the batch (blocks until all statuses are final). */
+osqp_int osqp_batch_solve(osqp_batch *b);
+/* Enqueue the solve on the batch's stream without waiting (results are
+ * valid after osqp_batch_sync). */
+osqp_int osqp_batch_solve_async(osqp_batch *b);
+osqp_int osqp_batch_sync(osqp_batch *b);
+/* Re-run the device-side Ruiz scaling from the resident unscaled data and
+ * reset every iterate to zero (a fresh solve of the same problems). */
+osqp_int osqp_batch_reset(osqp_batch *b);
+osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *q,
+                                   const osqp_float *l, const osqp_float *u);
+osqp_int osqp_batch_warm_start(osqp_batch *b, osqp_int i, const osqp_float *x,
+                               const osqp_float *y);
+/* Result of problem i: x (n_i), y (m_i) and info; any pointer may be NULL. */
+osqp_int osqp_batch_get(const osqp_batch *b, osqp_int i, osqp_float *x, osqp_float *y,
+                        osqp_info *info);
+/* Device time in milliseconds of the last solve's main kernel (HIP events on
+ * the batch's stream). */
+osqp_int osqp_batch_last_kernel_ms(const osqp_batch *b, double *ms);
+osqp_int osqp_batch_count(const osqp_batch *b, osqp_int *count);
+void osqp_batch_cleanup(osqp_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

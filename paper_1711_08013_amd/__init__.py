@@ -1,0 +1,264 @@
+"""Python binding of osqp_mi, the MI355X (gfx950) implementation of the
+operator-splitting ADMM QP method (OSQP paper).
+
+This module only marshals arguments into the C ABI of libosqp_mi.so
+(include/osqp_mi.h); every step of the solve runs in the library's HIP
+kernels.  There is no CPU fallback: a missing library or device raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libosqp_mi.so")
+
+STATUS = {1: "solved", 2: "primal_infeasible", 3: "dual_infeasible",
+          4: "max_iter_reached", 5: "time_limit_reached", 6: "unsolved"}
+ERRORS = {0: "ok", 1: "dim", 2: "csr", 3: "p_not_upper", 4: "data_nonfinite", 5: "l_gt_u",
+          6: "settings", 7: "alloc", 8: "budget", 9: "device", 10: "not_setup",
+          11: "index", 12: "no_device"}
+PRECISION = {"fp64": 0, "fp32": 1}
+LINSYS = {"auto": 0, "pcg": 1, "dense": 2}
+
+# every function the header declares (the CPU tests check the exports)
+EXPORTS = [
+    "osqp_set_default_settings", "osqp_error_string", "osqp_device_count", "osqp_setup",
+    "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_get_solution",
+    "osqp_get_info", "osqp_cleanup", "osqp_batch_setup", "osqp_batch_solve",
+    "osqp_batch_solve_async", "osqp_batch_sync", "osqp_batch_reset",
+    "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_get",
+    "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_cleanup",
+]
+
+
+class OSQPError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: error {code} ({ERRORS.get(code, '?')})")
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int32), ("ncols", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("data", ctypes.c_void_p)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("P_upper", _Csr),
+                ("q", ctypes.c_void_p), ("A", _Csr), ("l", ctypes.c_void_p),
+                ("u", ctypes.c_void_p)]
+
+
+_SET_F = ["rho", "sigma", "alpha", "eps_abs", "eps_rel", "eps_prim_inf", "eps_dual_inf",
+          "delta", "time_limit", "pcg_tol_frac"]
+_SET_I = ["max_iter", "check_every", "scaling_iters", "adaptive_rho", "polish",
+          "polish_refine_iter", "precision", "linsys", "pcg_max_iter", "block_size"]
+
+
+class _Settings(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in _SET_F] + \
+               [(k, ctypes.c_int32) for k in _SET_I] + [("stream", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in
+                ("status", "iter", "pcg_iter", "rho_updates", "polish_status")] + \
+               [(k, ctypes.c_double) for k in
+                ("obj_val", "prim_res", "dual_res", "eps_prim", "eps_dual", "rho_bar",
+                 "setup_time", "solve_time", "polish_time")]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libosqp_mi.so (built by paper_1711_08013_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1711_08013_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name in EXPORTS:
+            getattr(L, name)
+        L.osqp_error_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup"):
+                getattr(L, name).restype = ctypes.c_int32
+        L.osqp_cleanup.restype = None
+        L.osqp_batch_cleanup.restype = None
+        _lib = L
+    return _lib
+
+
+def device_count() -> int:
+    return int(lib().osqp_device_count())
+
+
+def default_settings() -> dict:
+    s = _Settings()
+    lib().osqp_set_default_settings(ctypes.byref(s))
+    return {k: getattr(s, k) for k in _SET_F + _SET_I}
+
+
+def _make_settings(kw: dict) -> _Settings:
+    s = _Settings()
+    lib().osqp_set_default_settings(ctypes.byref(s))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        if k == "linsys" and isinstance(v, str):
+            v = LINSYS[v]
+        if k == "stream":
+            s.stream = None if v is None else ctypes.c_void_p(int(v))
+            continue
+        if k not in _SET_F and k not in _SET_I:
+            raise KeyError(f"unknown setting {k}")
+        setattr(s, k, v)
+    return s
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
+
+
+class _Keep:
+    """Typed contiguous copies of one QP's arrays, kept alive during a call."""
+
+    def __init__(self, qp):
+        P = qp.P.tocsr()
+        A = qp.A.tocsr()
+        self.n, self.m = int(P.shape[0]), int(A.shape[0])
+        self.Pp = np.ascontiguousarray(P.indptr, dtype=np.int32)
+        self.Pi = np.ascontiguousarray(P.indices, dtype=np.int32)
+        self.Px = np.ascontiguousarray(P.data, dtype=np.float64)
+        self.Ap = np.ascontiguousarray(A.indptr, dtype=np.int32)
+        self.Ai = np.ascontiguousarray(A.indices, dtype=np.int32)
+        self.Ax = np.ascontiguousarray(A.data, dtype=np.float64)
+        self.q = np.ascontiguousarray(qp.q, dtype=np.float64)
+        self.l = np.ascontiguousarray(qp.l, dtype=np.float64)
+        self.u = np.ascontiguousarray(qp.u, dtype=np.float64)
+        self.pnnz, self.annz = int(P.nnz), int(A.nnz)
+
+    def problem(self) -> _Problem:
+        Pc = _Csr(self.n, self.n, self.pnnz, _ptr(self.Pp), _ptr(self.Pi), _ptr(self.Px))
+        Ac = _Csr(self.m, self.n, self.annz, _ptr(self.Ap), _ptr(self.Ai), _ptr(self.Ax))
+        return _Problem(self.n, self.m, Pc, _ptr(self.q), Ac, _ptr(self.l), _ptr(self.u))
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise OSQPError(int(rc), where)
+
+
+def _info_dict(info: _Info) -> dict:
+    d = {k: getattr(info, k) for k, _ in _Info._fields_}
+    d["status_name"] = STATUS.get(d["status"], "?")
+    return d
+
+
+class Batch:
+    """A batch of independent QPs solved together on the GPU (a single QP is a
+    batch of one).  `qps` are objects with P (upper-triangular scipy CSR), q,
+    A (scipy CSR), l, u."""
+
+    def __init__(self, qps: Sequence, **settings):
+        L = lib()
+        self._keep = [_Keep(qp) for qp in qps]
+        probs = (_Problem * len(self._keep))(*[k.problem() for k in self._keep])
+        self._settings = _make_settings(settings)
+        h = ctypes.c_void_p()
+        _check(L.osqp_batch_setup(ctypes.byref(h), len(self._keep), probs,
+                                  ctypes.byref(self._settings)), "osqp_batch_setup")
+        self._h = h
+        self.sizes = [(k.n, k.m) for k in self._keep]
+
+    def __len__(self):
+        return len(self._keep)
+
+    def solve(self):
+        _check(lib().osqp_batch_solve(self._h), "osqp_batch_solve")
+
+    def solve_async(self):
+        _check(lib().osqp_batch_solve_async(self._h), "osqp_batch_solve_async")
+
+    def sync(self):
+        _check(lib().osqp_batch_sync(self._h), "osqp_batch_sync")
+
+    def reset(self):
+        _check(lib().osqp_batch_reset(self._h), "osqp_batch_reset")
+
+    def update_vectors(self, i: int, q=None, l=None, u=None):
+        n, m = self.sizes[i]
+        qa = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        la = None if l is None else np.ascontiguousarray(l, dtype=np.float64)
+        ua = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+        for a, k in ((qa, n), (la, m), (ua, m)):
+            if a is not None and a.size != k:
+                raise ValueError("vector size mismatch")
+        _check(lib().osqp_batch_update_vectors(self._h, i, _ptr(qa), _ptr(la), _ptr(ua)),
+               "osqp_batch_update_vectors")
+
+    def warm_start(self, i: int, x=None, y=None):
+        n, m = self.sizes[i]
+        xa = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+        ya = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
+        if (xa is not None and xa.size != n) or (ya is not None and ya.size != m):
+            raise ValueError("vector size mismatch")
+        _check(lib().osqp_batch_warm_start(self._h, i, _ptr(xa), _ptr(ya)),
+               "osqp_batch_warm_start")
+
+    def get(self, i: int):
+        n, m = self.sizes[i]
+        x = np.zeros(n)
+        y = np.zeros(max(m, 1))
+        info = _Info()
+        _check(lib().osqp_batch_get(self._h, i, _ptr(x), _ptr(y), ctypes.byref(info)),
+               "osqp_batch_get")
+        return x, y[:m], _info_dict(info)
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().osqp_batch_last_kernel_ms(self._h, ctypes.byref(ms)),
+               "osqp_batch_last_kernel_ms")
+        return ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().osqp_batch_cleanup(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver(Batch):
+    """One QP (osqp_setup / osqp_solve / osqp_update_vectors / osqp_warm_start)."""
+
+    def __init__(self, qp, **settings):
+        super().__init__([qp], **settings)
+
+    def update_vectors(self, q=None, l=None, u=None):
+        super().update_vectors(0, q, l, u)
+
+    def warm_start(self, x=None, y=None):
+        super().warm_start(0, x, y)
+
+    def result(self):
+        return super().get(0)
+
+
+def solve(qp, **settings):
+    """Convenience: set up, solve and return (x, y, info) for one QP."""
+    s = Solver(qp, **settings)
+    try:
+        s.solve()
+        return s.result()
+    finally:
+        s.close()

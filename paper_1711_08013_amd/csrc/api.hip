@@ -1,0 +1,890 @@
+// Host side of osqp_mi: input validation, pattern construction (full
+// symmetric P, rows of A'), packing of a batch into one device arena, kernel
+// launches and the C ABI declared in include/osqp_mi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "osqp_mi.h"
+#include "kernels.h"
+
+using namespace osqpmi;
+
+namespace {
+
+constexpr double kInfBound = 1e30;
+constexpr int kPolishMaxN = 3000;   // largest n polished with a dense condensed system
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int check_csr(const osqp_csr *M, int rows, int cols) {
+  if (!M) return OSQP_ERR_NOT_SETUP;
+  if (M->nrows != rows || M->ncols != cols || M->nnz < 0) return OSQP_ERR_DIM;
+  if (rows > 0 && !M->indptr) return OSQP_ERR_CSR;
+  if (M->nnz > 0 && (!M->indices || !M->data)) return OSQP_ERR_CSR;
+  if (rows == 0) return (M->nnz == 0) ? OSQP_OK : OSQP_ERR_CSR;
+  if (M->indptr[0] != 0 || M->indptr[rows] != M->nnz) return OSQP_ERR_CSR;
+  for (int i = 0; i < rows; ++i) {
+    const int b = M->indptr[i], e = M->indptr[i + 1];
+    if (e < b || e > M->nnz) return OSQP_ERR_CSR;
+    int prev = -1;
+    for (int k = b; k < e; ++k) {
+      const int j = M->indices[k];
+      if (j < 0 || j >= cols || j <= prev) return OSQP_ERR_CSR;
+      prev = j;
+      if (!std::isfinite(M->data[k])) return OSQP_ERR_DATA_NONFINITE;
+    }
+  }
+  return OSQP_OK;
+}
+
+int check_problem(const osqp_problem &p) {
+  if (p.n <= 0 || p.m < 0) return OSQP_ERR_DIM;
+  int rc = check_csr(&p.P_upper, p.n, p.n);
+  if (rc) return rc;
+  rc = check_csr(&p.A, p.m, p.n);
+  if (rc) return rc;
+  for (int i = 0; i < p.n; ++i)
+    for (int k = p.P_upper.indptr[i]; k < p.P_upper.indptr[i + 1]; ++k)
+      if (p.P_upper.indices[k] < i) return OSQP_ERR_P_NOT_UPPER;
+  if (!p.q || (p.m > 0 && (!p.l || !p.u))) return OSQP_ERR_NOT_SETUP;
+  for (int j = 0; j < p.n; ++j)
+    if (!std::isfinite(p.q[j])) return OSQP_ERR_DATA_NONFINITE;
+  for (int i = 0; i < p.m; ++i) {
+    if (std::isnan(p.l[i]) || std::isnan(p.u[i])) return OSQP_ERR_DATA_NONFINITE;
+    if (p.l[i] > p.u[i]) return OSQP_ERR_L_GT_U;
+  }
+  return OSQP_OK;
+}
+
+int check_settings(const osqp_settings &s) {
+  if (!(s.rho > 0) || !(s.sigma > 0) || !(s.alpha > 0 && s.alpha < 2)) return OSQP_ERR_SETTINGS;
+  if (!(s.eps_abs >= 0) || !(s.eps_rel >= 0) || !(s.eps_prim_inf >= 0) ||
+      !(s.eps_dual_inf >= 0) || !(s.delta > 0) || !(s.time_limit >= 0) ||
+      !(s.pcg_tol_frac > 0))
+    return OSQP_ERR_SETTINGS;
+  if (s.max_iter <= 0 || s.check_every <= 0 || s.scaling_iters < 0 || s.polish_refine_iter < 0 ||
+      s.pcg_max_iter <= 0)
+    return OSQP_ERR_SETTINGS;
+  if (s.precision != OSQP_PRECISION_FP64 && s.precision != OSQP_PRECISION_FP32_MIXED)
+    return OSQP_ERR_SETTINGS;
+  if (s.linsys < 0 || s.linsys > 2) return OSQP_ERR_SETTINGS;
+  if (s.block_size != 0 && (s.block_size < 64 || s.block_size > kMaxBlock || s.block_size % 64))
+    return OSQP_ERR_SETTINGS;
+  return OSQP_OK;
+}
+
+int pow2_lanes(double avg) {
+  // lanes per row: about half the average row length, a power of two in [1, 64]
+  int L = 1;
+  while (L < 64 && 2.0 * L < avg) L <<= 1;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// device arena
+// ---------------------------------------------------------------------------
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+  template <class T>
+  T *take(size_t count) {
+    size_t bytes = ((count * sizeof(T)) + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    T *p = reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the batch object
+// ---------------------------------------------------------------------------
+struct osqp_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  osqp_settings set{};
+  int nq = 0;
+  bool fp64 = false;
+  std::vector<QPDesc> desc;
+  std::vector<int> small_list, big_list;   // workgroup-team QPs / grid-team QPs
+  int64_t sum_n = 0, sum_m = 0, nnz_a = 0, nnz_p = 0;
+  // host staging of the inputs that change through the parametric API
+  std::vector<double> q_raw, l_raw, u_raw;
+  std::vector<unsigned char> is_eq;
+  // device
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  Batch<double> bd{};
+  Batch<float> bf{};
+  int *d_small = nullptr, *d_big = nullptr;
+  double *d_partials = nullptr;
+  GridBarrier *d_bar = nullptr;
+  int block = 256, grid_wg = 0, grid_coop = 0, coop_block = 256;
+  // polishing workspace (one slot per resident polish workgroup)
+  std::vector<int> polish_list;
+  int *d_polish = nullptr;
+  double *d_pws = nullptr;
+  long long pws_stride = 0;
+  int polish_rmax = 0, polish_slots = 0;
+  // results on the host
+  std::vector<QPState> st;
+  std::vector<double> xo, yo;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double setup_time = 0.0, last_solve_time = 0.0;
+  double wall_tick_s = 1e-8;
+  bool solved_once = false;
+
+  DevSettings dev_settings() const {
+    DevSettings d{};
+    d.sigma = set.sigma; d.alpha = set.alpha; d.eps_abs = set.eps_abs; d.eps_rel = set.eps_rel;
+    d.eps_pinf = set.eps_prim_inf; d.eps_dinf = set.eps_dual_inf; d.delta = set.delta;
+    d.time_limit = set.time_limit; d.pcg_tol_frac = set.pcg_tol_frac;
+    d.max_iter = set.max_iter; d.check_every = set.check_every;
+    d.scaling_iters = set.scaling_iters; d.adaptive_rho = set.adaptive_rho;
+    d.polish = set.polish; d.refine = set.polish_refine_iter; d.pcg_max_iter = set.pcg_max_iter;
+    d.wall_tick_s = wall_tick_s;
+    return d;
+  }
+};
+
+namespace {
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return OSQP_ERR_DEVICE; \
+  } while (0)
+
+template <class T>
+void fill_batch_ptrs(Batch<T> &B, osqp_batch *b, Arena &ar, bool alias64) {
+  const int64_t sn = b->sum_n, sm = b->sum_m, na = b->nnz_a, np = b->nnz_p;
+  const int nq = b->nq;
+  B.desc = ar.take<QPDesc>(nq);
+  B.st = ar.take<QPState>(nq);
+  B.nq = nq;
+  B.counter = ar.take<int>(64);
+  B.a_rp = ar.take<int>(sm + nq);
+  B.at_rp = ar.take<int>(sn + nq);
+  B.p_rp = ar.take<int>(sn + nq);
+  B.a_ci = ar.take<int>(na);
+  B.at_ci = ar.take<int>(na);
+  B.p_ci = ar.take<int>(np);
+  B.a_raw = ar.take<double>(na);
+  B.at_raw = ar.take<double>(na);
+  B.p_raw = ar.take<double>(np);
+  B.q_raw = ar.take<double>(sn);
+  B.l_raw = ar.take<double>(sm);
+  B.u_raw = ar.take<double>(sm);
+  B.a64 = ar.take<double>(na);
+  B.at64 = ar.take<double>(na);
+  B.p64 = ar.take<double>(np);
+  B.q64 = ar.take<double>(sn);
+  B.l64 = ar.take<double>(sm);
+  B.u64 = ar.take<double>(sm);
+  if (alias64) {
+    B.a_v = reinterpret_cast<T *>(B.a64);
+    B.at_v = reinterpret_cast<T *>(B.at64);
+    B.p_v = reinterpret_cast<T *>(B.p64);
+    B.q = reinterpret_cast<T *>(B.q64);
+    B.l = reinterpret_cast<T *>(B.l64);
+    B.u = reinterpret_cast<T *>(B.u64);
+  } else {
+    B.a_v = ar.take<T>(na);
+    B.at_v = ar.take<T>(na);
+    B.p_v = ar.take<T>(np);
+    B.q = ar.take<T>(sn);
+    B.l = ar.take<T>(sm);
+    B.u = ar.take<T>(sm);
+  }
+  B.pdiag = ar.take<T>(sn);
+  B.D = ar.take<double>(sn);
+  B.E = ar.take<double>(sm);
+  B.Dinv = ar.take<double>(sn);
+  B.Einv = ar.take<double>(sm);
+  B.is_eq = ar.take<unsigned char>(sm);
+  B.rho = ar.take<T>(sm);
+  B.rhoinv = ar.take<T>(sm);
+  B.minv = ar.take<T>(sn);
+  B.x = ar.take<T>(sn);
+  B.z = ar.take<T>(sm);
+  B.y = ar.take<T>(sm);
+  B.xt = ar.take<T>(sn);
+  B.zt = ar.take<T>(sm);
+  B.r = ar.take<T>(sn);
+  B.d = ar.take<T>(sn);
+  B.p = ar.take<T>(sn);
+  B.w = ar.take<T>(sn);
+  B.t = ar.take<T>(sm);
+  B.s = ar.take<T>(sm);
+  B.dx = ar.take<double>(sn);
+  B.dy = ar.take<double>(sm);
+  B.xws = ar.take<double>(sn);
+  B.yws = ar.take<double>(sm);
+  B.xo = ar.take<double>(sn);
+  B.yo = ar.take<double>(sm);
+  B.zo = ar.take<double>(sm);
+}
+
+template <class T>
+size_t arena_bytes_for(osqp_batch *b, bool alias64) {
+  Arena probe;
+  probe.base = nullptr;
+  Batch<T> B{};
+  fill_batch_ptrs(B, b, probe, alias64);
+  return probe.used + 4096;
+}
+
+template <class T>
+Batch<T> &batch_of(osqp_batch *b);
+template <>
+Batch<double> &batch_of<double>(osqp_batch *b) { return b->bd; }
+template <>
+Batch<float> &batch_of<float>(osqp_batch *b) { return b->bf; }
+
+template <class T>
+int launch_scale(osqp_batch *b) {
+  Batch<T> &B = batch_of<T>(b);
+  B.set = b->dev_settings();
+  reset_counters_kernel<<<1, 64, 0, b->stream>>>(B.counter, 64, b->d_bar);
+  if (!b->small_list.empty()) {
+    const int nl = (int)b->small_list.size();
+    const int grid = std::max(1, std::min(nl, b->grid_wg));
+    scale_wg_kernel<T><<<grid, b->block, 0, b->stream>>>(B, b->d_small, nl, 0);
+  }
+  if (!b->big_list.empty()) {
+    const int nl = (int)b->big_list.size();
+    void *args[] = {&B, &b->d_big, (void *)&nl, &b->d_partials, &b->d_bar};
+    HIPCHK(hipLaunchCooperativeKernel((const void *)scale_grid_kernel<T>, dim3(b->grid_coop),
+                                      dim3(b->coop_block), args, 0, b->stream));
+  }
+  HIPCHK(hipGetLastError());
+  return OSQP_OK;
+}
+
+template <class T>
+int launch_solve(osqp_batch *b) {
+  Batch<T> &B = batch_of<T>(b);
+  B.set = b->dev_settings();
+  reset_counters_kernel<<<1, 64, 0, b->stream>>>(B.counter, 64, b->d_bar);
+  HIPCHK(hipEventRecord(b->ev0, b->stream));
+  if (!b->big_list.empty()) {
+    const int nl = (int)b->big_list.size();
+    void *args[] = {&B, &b->d_big, (void *)&nl, &b->d_partials, &b->d_bar};
+    HIPCHK(hipLaunchCooperativeKernel((const void *)solve_grid_kernel<T>, dim3(b->grid_coop),
+                                      dim3(b->coop_block), args, 0, b->stream));
+  }
+  if (!b->small_list.empty()) {
+    const int nl = (int)b->small_list.size();
+    const int grid = std::max(1, std::min(nl, b->grid_wg));
+    solve_wg_kernel<T><<<grid, b->block, 0, b->stream>>>(B, b->d_small, nl, 1);
+  }
+  HIPCHK(hipEventRecord(b->ev1, b->stream));
+  if (b->set.polish && !b->polish_list.empty()) {
+    const int nl = (int)b->polish_list.size();
+    polish_wg_kernel<T><<<b->polish_slots, kPolishBlock, 0, b->stream>>>(
+        B, b->d_polish, nl, 2, b->d_pws, b->pws_stride, b->polish_rmax);
+  }
+  HIPCHK(hipGetLastError());
+  return OSQP_OK;
+}
+
+int fetch_results(osqp_batch *b) {
+  const Batch<double> &B = b->bd;
+  const QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
+  const double *dxo = b->fp64 ? b->bd.xo : b->bf.xo;
+  const double *dyo = b->fp64 ? b->bd.yo : b->bf.yo;
+  (void)B;
+  HIPCHK(hipMemcpyAsync(b->st.data(), dst, sizeof(QPState) * b->nq, hipMemcpyDeviceToHost,
+                        b->stream));
+  HIPCHK(hipMemcpyAsync(b->xo.data(), dxo, sizeof(double) * b->sum_n, hipMemcpyDeviceToHost,
+                        b->stream));
+  if (b->sum_m > 0)
+    HIPCHK(hipMemcpyAsync(b->yo.data(), dyo, sizeof(double) * b->sum_m, hipMemcpyDeviceToHost,
+                          b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return OSQP_OK;
+}
+
+void destroy(osqp_batch *b) {
+  if (!b) return;
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->d_pws) (void)hipFree(b->d_pws);
+  if (b->d_polish) (void)hipFree(b->d_polish);
+  if (b->d_small) (void)hipFree(b->d_small);
+  if (b->d_big) (void)hipFree(b->d_big);
+  if (b->d_partials) (void)hipFree(b->d_partials);
+  if (b->d_bar) (void)hipFree(b->d_bar);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
+                     const osqp_settings *s_in) {
+  if (!out) return OSQP_ERR_NOT_SETUP;
+  *out = nullptr;
+  if (count <= 0 || !probs) return OSQP_ERR_DIM;
+  osqp_settings s;
+  if (s_in) s = *s_in; else osqp_set_default_settings(&s);
+  int rc = check_settings(s);
+  if (rc) return rc;
+  for (int k = 0; k < count; ++k) {
+    rc = check_problem(probs[k]);
+    if (rc) return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return OSQP_ERR_NO_DEVICE;
+
+  const double t0 = now_s();
+  osqp_batch *b = new (std::nothrow) osqp_batch();
+  if (!b) return OSQP_ERR_ALLOC;
+  b->set = s;
+  b->nq = count;
+  b->fp64 = (s.precision == OSQP_PRECISION_FP64);
+  if (hipGetDevice(&b->device) != hipSuccess) { destroy(b); return OSQP_ERR_DEVICE; }
+  if (s.stream) {
+    b->stream = (hipStream_t)s.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      destroy(b);
+      return OSQP_ERR_DEVICE;
+    }
+    b->own_stream = true;
+  }
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+    destroy(b);
+    return OSQP_ERR_DEVICE;
+  }
+
+  // ---- sizes, offsets, patterns (host) ------------------------------------
+  b->desc.resize(count);
+  std::vector<int64_t> pfull_nnz(count);
+  for (int k = 0; k < count; ++k) {
+    const osqp_problem &p = probs[k];
+    int64_t diag = 0;
+    for (int i = 0; i < p.n; ++i)
+      for (int e = p.P_upper.indptr[i]; e < p.P_upper.indptr[i + 1]; ++e)
+        diag += (p.P_upper.indices[e] == i);
+    pfull_nnz[k] = 2 * (int64_t)p.P_upper.nnz - diag;
+    QPDesc &d = b->desc[k];
+    d.n = p.n; d.m = p.m;
+    d.xo = b->sum_n; d.yo = b->sum_m;
+    d.a_rp = b->sum_m + k; d.at_rp = b->sum_n + k; d.p_rp = b->sum_n + k;
+    d.a_nz = b->nnz_a; d.at_nz = b->nnz_a; d.p_nz = b->nnz_p;
+    d.lm = pow2_lanes(p.m > 0 ? double(p.A.nnz) / p.m : 1.0);
+    d.ln = pow2_lanes(double(pfull_nnz[k] + p.A.nnz) / p.n);
+    d.dense_off = 0;
+    b->sum_n += p.n; b->sum_m += p.m; b->nnz_a += p.A.nnz; b->nnz_p += pfull_nnz[k];
+  }
+  // which QPs get the whole grid: large enough that one workgroup would be
+  // the bottleneck of the batch
+  std::vector<int64_t> cost(count);
+  int64_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    cost[k] = 2 * probs[k].A.nnz + pfull_nnz[k] + probs[k].n + probs[k].m;
+    total += cost[k];
+  }
+  for (int k = 0; k < count; ++k) {
+    const bool big = cost[k] >= (int64_t)400000 && (count == 1 || cost[k] * 64 > total);
+    (big ? b->big_list : b->small_list).push_back(k);
+  }
+  std::stable_sort(b->small_list.begin(), b->small_list.end(),
+                   [&](int a, int c) { return cost[a] > cost[c]; });
+
+  const bool alias = b->fp64;
+  b->arena_bytes = b->fp64 ? arena_bytes_for<double>(b, true) : arena_bytes_for<float>(b, false);
+  if (hipMalloc(&b->arena, b->arena_bytes) != hipSuccess) {
+    b->arena = nullptr;
+    destroy(b);
+    return OSQP_ERR_ALLOC;
+  }
+  Arena ar;
+  ar.base = b->arena;
+  ar.size = b->arena_bytes;
+  if (b->fp64) fill_batch_ptrs(b->bd, b, ar, alias);
+  else fill_batch_ptrs(b->bf, b, ar, alias);
+  // the double-precision Batch is the one the host reads results from in
+  // both modes; keep its pointers valid for the mixed mode too
+  if (!b->fp64) {
+    Batch<double> &D = b->bd;
+    const Batch<float> &F = b->bf;
+    D.desc = F.desc; D.st = F.st; D.xo = F.xo; D.yo = F.yo; D.zo = F.zo;
+  }
+
+  // host packing
+  const int64_t sn = b->sum_n, sm = b->sum_m, na = b->nnz_a, np = b->nnz_p;
+  std::vector<int> a_rp(sm + count), at_rp(sn + count), p_rp(sn + count);
+  std::vector<int> a_ci(na), at_ci(na), p_ci(np);
+  std::vector<double> a_raw(na), at_raw(na), p_raw(np);
+  b->q_raw.resize(sn); b->l_raw.resize(sm); b->u_raw.resize(sm); b->is_eq.resize(sm);
+  for (int k = 0; k < count; ++k) {
+    const osqp_problem &p = probs[k];
+    const QPDesc &d = b->desc[k];
+    const int n = p.n, m = p.m;
+    // A rows
+    for (int i = 0; i <= m; ++i) a_rp[d.a_rp + i] = p.A.indptr[i];
+    std::memcpy(&a_ci[d.a_nz], p.A.indices, sizeof(int) * p.A.nnz);
+    std::memcpy(&a_raw[d.a_nz], p.A.data, sizeof(double) * p.A.nnz);
+    // A' rows (counting sort by column; rows come out in increasing order)
+    std::vector<int> cnt(n + 1, 0);
+    for (int e = 0; e < p.A.nnz; ++e) cnt[p.A.indices[e] + 1]++;
+    for (int j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
+    for (int j = 0; j <= n; ++j) at_rp[d.at_rp + j] = cnt[j];
+    std::vector<int> nxt(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < m; ++i)
+      for (int e = p.A.indptr[i]; e < p.A.indptr[i + 1]; ++e) {
+        const int j = p.A.indices[e];
+        const int pos = nxt[j]++;
+        at_ci[d.at_nz + pos] = i;
+        at_raw[d.at_nz + pos] = p.A.data[e];
+      }
+    // full symmetric P from the upper triangle (rows stay sorted: the lower
+    // part of row j comes from rows i < j, appended in increasing i)
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int i = 0; i < n; ++i)
+      for (int e = p.P_upper.indptr[i]; e < p.P_upper.indptr[i + 1]; ++e) {
+        const int j = p.P_upper.indices[e];
+        cnt[i + 1]++;
+        if (j != i) cnt[j + 1]++;
+      }
+    for (int j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
+    for (int j = 0; j <= n; ++j) p_rp[d.p_rp + j] = cnt[j];
+    std::vector<int> pn(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int e = p.P_upper.indptr[i]; e < p.P_upper.indptr[i + 1]; ++e) {
+        const int j = p.P_upper.indices[e];
+        const double v = p.P_upper.data[e];
+        int pos = pn[i]++;
+        p_ci[d.p_nz + pos] = j;
+        p_raw[d.p_nz + pos] = v;
+        if (j != i) {
+          pos = pn[j]++;
+          p_ci[d.p_nz + pos] = i;
+          p_raw[d.p_nz + pos] = v;
+        }
+      }
+    // vectors; |b| >= 1e30 is an infinite bound
+    std::memcpy(&b->q_raw[d.xo], p.q, sizeof(double) * n);
+    for (int i = 0; i < m; ++i) {
+      const double lo = p.l[i] <= -kInfBound ? -INFINITY : p.l[i];
+      const double hi = p.u[i] >= kInfBound ? INFINITY : p.u[i];
+      b->l_raw[d.yo + i] = lo;
+      b->u_raw[d.yo + i] = hi;
+      b->is_eq[d.yo + i] = (lo == hi);   // reading: exact equality on the input
+    }
+  }
+  std::vector<QPState> st0(count);
+  for (int k = 0; k < count; ++k) {
+    std::memset(&st0[k], 0, sizeof(QPState));
+    st0[k].rho_bar = s.rho;
+    st0[k].c = 1.0;
+    st0[k].init_mode = 1;
+    st0[k].status = OSQP_UNSOLVED;
+  }
+  b->st = st0;
+  b->xo.assign(sn, 0.0);
+  b->yo.assign(sm, 0.0);
+
+  auto up = [&](void *dst, const void *src, size_t bytes) -> bool {
+    if (bytes == 0) return true;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  };
+  auto upload = [&](auto &B) -> bool {
+    bool ok = true;
+    ok &= up((void *)B.desc, b->desc.data(), sizeof(QPDesc) * count);
+    ok &= up((void *)B.st, st0.data(), sizeof(QPState) * count);
+    ok &= up((void *)B.a_rp, a_rp.data(), sizeof(int) * a_rp.size());
+    ok &= up((void *)B.at_rp, at_rp.data(), sizeof(int) * at_rp.size());
+    ok &= up((void *)B.p_rp, p_rp.data(), sizeof(int) * p_rp.size());
+    ok &= up((void *)B.a_ci, a_ci.data(), sizeof(int) * na);
+    ok &= up((void *)B.at_ci, at_ci.data(), sizeof(int) * na);
+    ok &= up((void *)B.p_ci, p_ci.data(), sizeof(int) * np);
+    ok &= up((void *)B.a_raw, a_raw.data(), sizeof(double) * na);
+    ok &= up((void *)B.at_raw, at_raw.data(), sizeof(double) * na);
+    ok &= up((void *)B.p_raw, p_raw.data(), sizeof(double) * np);
+    ok &= up((void *)B.q_raw, b->q_raw.data(), sizeof(double) * sn);
+    ok &= up((void *)B.l_raw, b->l_raw.data(), sizeof(double) * sm);
+    ok &= up((void *)B.u_raw, b->u_raw.data(), sizeof(double) * sm);
+    ok &= up((void *)B.is_eq, b->is_eq.data(), sm);
+    return ok;
+  };
+  bool ok = b->fp64 ? upload(b->bd) : upload(b->bf);
+  if (!ok) { destroy(b); return OSQP_ERR_DEVICE; }
+
+  // ---- launch geometry ------------------------------------------------------
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { destroy(b); return OSQP_ERR_DEVICE; }
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess ||
+      wall_khz <= 0)
+    wall_khz = 100000;
+  b->wall_tick_s = 1.0 / (1e3 * wall_khz);
+  b->block = s.block_size ? s.block_size : 256;
+  int per_cu = 1;
+  if (b->fp64)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<double>, b->block, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<float>, b->block, 0);
+  per_cu = std::max(1, per_cu);
+  b->grid_wg = prop.multiProcessorCount * per_cu;
+  b->coop_block = 256;
+  int coop_per_cu = 1;
+  if (b->fp64)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&coop_per_cu, solve_grid_kernel<double>,
+                                                       b->coop_block, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&coop_per_cu, solve_grid_kernel<float>,
+                                                       b->coop_block, 0);
+  // one workgroup per CU keeps the grid barrier cheap; never more than resident
+  b->grid_coop = prop.multiProcessorCount * std::min(1, std::max(1, coop_per_cu));
+  if (!b->big_list.empty()) {
+    if (hipMalloc(&b->d_partials, sizeof(double) * 2 * kRedSlots * b->grid_coop) != hipSuccess ||
+        hipMalloc(&b->d_bar, sizeof(GridBarrier)) != hipSuccess) {
+      destroy(b);
+      return OSQP_ERR_ALLOC;
+    }
+  }
+  // lists
+  if (hipMalloc(&b->d_small, sizeof(int) * std::max<size_t>(1, b->small_list.size())) != hipSuccess ||
+      hipMalloc(&b->d_big, sizeof(int) * std::max<size_t>(1, b->big_list.size())) != hipSuccess) {
+    destroy(b);
+    return OSQP_ERR_ALLOC;
+  }
+  if (!up(b->d_small, b->small_list.data(), sizeof(int) * b->small_list.size()) ||
+      !up(b->d_big, b->big_list.data(), sizeof(int) * b->big_list.size())) {
+    destroy(b);
+    return OSQP_ERR_DEVICE;
+  }
+  // polishing workspace: QPs with n <= kPolishMaxN get a dense condensed
+  // system; larger ones are reported as "polish not run"
+  if (s.polish) {
+    int nmax = 0, mmax = 0, rmax = 0;
+    for (int k = 0; k < count; ++k) {
+      const osqp_problem &p = probs[k];
+      if (p.n > kPolishMaxN) continue;
+      b->polish_list.push_back(k);
+      nmax = std::max(nmax, p.n);
+      mmax = std::max(mmax, p.m);
+      int multi = 0;
+      for (int i = 0; i < p.m; ++i) multi += (p.A.indptr[i + 1] - p.A.indptr[i]) >= 2;
+      rmax = std::max(rmax, multi);
+    }
+    if (!b->polish_list.empty()) {
+      std::stable_sort(b->polish_list.begin(), b->polish_list.end(),
+                       [&](int a, int c) { return probs[a].n > probs[c].n; });
+      b->polish_rmax = rmax;
+      b->pws_stride = (long long)nmax * nmax + (long long)rmax * nmax + 3LL * nmax +
+                      5LL * mmax + 64;
+      b->polish_slots = std::max(1, std::min((int)b->polish_list.size(),
+                                             prop.multiProcessorCount));
+      if (hipMalloc(&b->d_pws, sizeof(double) * b->pws_stride * b->polish_slots) != hipSuccess ||
+          hipMalloc(&b->d_polish, sizeof(int) * b->polish_list.size()) != hipSuccess) {
+        b->d_pws = nullptr;
+        destroy(b);
+        return OSQP_ERR_ALLOC;
+      }
+      if (!up(b->d_polish, b->polish_list.data(), sizeof(int) * b->polish_list.size())) {
+        destroy(b);
+        return OSQP_ERR_DEVICE;
+      }
+    }
+  }
+  rc = b->fp64 ? launch_scale<double>(b) : launch_scale<float>(b);
+  if (rc == OSQP_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = OSQP_ERR_DEVICE;
+  if (rc) { destroy(b); return rc; }
+  b->setup_time = now_s() - t0;
+  *out = b;
+  return OSQP_OK;
+}
+
+void fill_info(const osqp_batch *b, int k, osqp_info *info) {
+  const QPState &S = b->st[k];
+  info->status = S.status;
+  info->iter = S.iter;
+  info->pcg_iter = S.pcg_iter;
+  info->rho_updates = S.rho_updates;
+  info->polish_status = S.polish_status;
+  info->obj_val = S.obj;
+  info->prim_res = S.prim_res;
+  info->dual_res = S.dual_res;
+  info->eps_prim = S.eps_prim;
+  info->eps_dual = S.eps_dual;
+  info->rho_bar = S.rho_bar;
+  info->setup_time = b->setup_time;
+  info->solve_time = b->nq == 1 ? b->last_solve_time : S.solve_ms * 1e-3;
+  info->polish_time = S.polish_ms * 1e-3;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+osqp_int osqp_set_default_settings(osqp_settings *s) {
+  if (!s) return OSQP_ERR_NOT_SETUP;
+  std::memset(s, 0, sizeof(*s));
+  s->rho = 0.1;
+  s->sigma = 1e-6;
+  s->alpha = 1.6;
+  s->eps_abs = 1e-3;
+  s->eps_rel = 1e-3;
+  s->eps_prim_inf = 1e-4;
+  s->eps_dual_inf = 1e-4;
+  s->delta = 1e-6;
+  s->time_limit = 0.0;
+  s->pcg_tol_frac = 0.15;
+  s->max_iter = 4000;
+  s->check_every = 25;
+  s->scaling_iters = 10;
+  s->adaptive_rho = 1;
+  s->polish = 0;
+  s->polish_refine_iter = 3;
+  s->precision = OSQP_PRECISION_FP32_MIXED;
+  s->linsys = OSQP_LINSYS_AUTO;
+  s->pcg_max_iter = 50;
+  s->block_size = 0;
+  s->stream = nullptr;
+  return OSQP_OK;
+}
+
+const char *osqp_error_string(osqp_int code) {
+  switch (code) {
+    case OSQP_OK: return "ok";
+    case OSQP_ERR_DIM: return "bad dimensions";
+    case OSQP_ERR_CSR: return "malformed CSR matrix";
+    case OSQP_ERR_P_NOT_UPPER: return "P has an entry below the diagonal";
+    case OSQP_ERR_DATA_NONFINITE: return "non-finite problem data";
+    case OSQP_ERR_L_GT_U: return "lower bound above upper bound";
+    case OSQP_ERR_SETTINGS: return "invalid settings";
+    case OSQP_ERR_ALLOC: return "allocation failed";
+    case OSQP_ERR_BUDGET: return "request exceeds the HBM budget";
+    case OSQP_ERR_DEVICE: return "HIP runtime error";
+    case OSQP_ERR_NOT_SETUP: return "handle or data missing";
+    case OSQP_ERR_INDEX: return "index out of range";
+    case OSQP_ERR_NO_DEVICE: return "no HIP device";
+    default: return "unknown error";
+  }
+}
+
+osqp_int osqp_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+osqp_int osqp_batch_setup(osqp_batch **out, osqp_int count, const osqp_problem *probs,
+                          const osqp_settings *s) {
+  try {
+    return batch_setup_impl(out, count, probs, s);
+  } catch (...) {
+    return OSQP_ERR_ALLOC;
+  }
+}
+
+osqp_int osqp_setup(osqp_solver **out, osqp_int n, osqp_int m, const osqp_csr *P_upper,
+                    const osqp_float *q, const osqp_csr *A, const osqp_float *l,
+                    const osqp_float *u, const osqp_settings *s) {
+  if (!out) return OSQP_ERR_NOT_SETUP;
+  *out = nullptr;
+  if (!P_upper || !A) return OSQP_ERR_NOT_SETUP;
+  osqp_problem p;
+  p.n = n; p.m = m; p.P_upper = *P_upper; p.q = q; p.A = *A; p.l = l; p.u = u;
+  return osqp_batch_setup(out, 1, &p, s);
+}
+
+osqp_int osqp_batch_solve_async(osqp_batch *b) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  try {
+    return b->fp64 ? launch_solve<double>(b) : launch_solve<float>(b);
+  } catch (...) {
+    return OSQP_ERR_DEVICE;
+  }
+}
+
+osqp_int osqp_batch_sync(osqp_batch *b) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  int rc = fetch_results(b);
+  if (rc) return rc;
+  if (b->d_bar) {
+    GridBarrier gb;
+    if (hipMemcpy(&gb, b->d_bar, sizeof(gb), hipMemcpyDeviceToHost) != hipSuccess)
+      return OSQP_ERR_DEVICE;
+    if (gb.timeout) return OSQP_ERR_DEVICE;
+  }
+  b->solved_once = true;
+  return OSQP_OK;
+}
+
+osqp_int osqp_batch_solve(osqp_batch *b) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  const double t0 = now_s();
+  int rc = osqp_batch_solve_async(b);
+  if (rc) return rc;
+  rc = osqp_batch_sync(b);
+  b->last_solve_time = now_s() - t0;
+  return rc;
+}
+
+osqp_int osqp_solve(osqp_solver *h) { return osqp_batch_solve(h); }
+
+osqp_int osqp_batch_reset(osqp_batch *b) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  // zero iterates, reset rho-bar, rescale from the resident raw data
+  std::vector<QPState> st0(b->nq);
+  for (int k = 0; k < b->nq; ++k) {
+    std::memset(&st0[k], 0, sizeof(QPState));
+    st0[k].rho_bar = b->set.rho;
+    st0[k].c = 1.0;
+    st0[k].init_mode = 1;
+    st0[k].status = OSQP_UNSOLVED;
+  }
+  QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
+  if (hipMemcpyAsync(dst, st0.data(), sizeof(QPState) * b->nq, hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess)
+    return OSQP_ERR_DEVICE;
+  int rc = b->fp64 ? launch_scale<double>(b) : launch_scale<float>(b);
+  if (rc) return rc;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return OSQP_ERR_DEVICE;
+  return OSQP_OK;
+}
+
+osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *q,
+                                   const osqp_float *l, const osqp_float *u) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
+  const QPDesc &d = b->desc[i];
+  if (q)
+    for (int j = 0; j < d.n; ++j)
+      if (!std::isfinite(q[j])) return OSQP_ERR_DATA_NONFINITE;
+  for (int k = 0; k < d.m; ++k) {
+    const double lo = l ? l[k] : b->l_raw[d.yo + k];
+    const double hi = u ? u[k] : b->u_raw[d.yo + k];
+    if (std::isnan(lo) || std::isnan(hi)) return OSQP_ERR_DATA_NONFINITE;
+    if (lo > hi) return OSQP_ERR_L_GT_U;
+  }
+  if (q) std::memcpy(&b->q_raw[d.xo], q, sizeof(double) * d.n);
+  for (int k = 0; k < d.m; ++k) {
+    if (l) b->l_raw[d.yo + k] = l[k] <= -kInfBound ? -INFINITY : l[k];
+    if (u) b->u_raw[d.yo + k] = u[k] >= kInfBound ? INFINITY : u[k];
+    b->is_eq[d.yo + k] = b->l_raw[d.yo + k] == b->u_raw[d.yo + k];
+  }
+  auto push = [&](auto &B) -> int {
+    HIPCHK(hipMemcpyAsync((void *)(B.q_raw + d.xo), &b->q_raw[d.xo], sizeof(double) * d.n,
+                          hipMemcpyHostToDevice, b->stream));
+    if (d.m > 0) {
+      HIPCHK(hipMemcpyAsync((void *)(B.l_raw + d.yo), &b->l_raw[d.yo], sizeof(double) * d.m,
+                            hipMemcpyHostToDevice, b->stream));
+      HIPCHK(hipMemcpyAsync((void *)(B.u_raw + d.yo), &b->u_raw[d.yo], sizeof(double) * d.m,
+                            hipMemcpyHostToDevice, b->stream));
+      HIPCHK(hipMemcpyAsync((void *)(B.is_eq + d.yo), &b->is_eq[d.yo], d.m,
+                            hipMemcpyHostToDevice, b->stream));
+    }
+    return OSQP_OK;
+  };
+  int rc = b->fp64 ? push(b->bd) : push(b->bf);
+  if (rc) return rc;
+  if (b->fp64)
+    rescale_vectors_wg_kernel<double><<<1, 256, 0, b->stream>>>(b->bd, i);
+  else
+    rescale_vectors_wg_kernel<float><<<1, 256, 0, b->stream>>>(b->bf, i);
+  if (hipGetLastError() != hipSuccess) return OSQP_ERR_DEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return OSQP_ERR_DEVICE;
+  return OSQP_OK;
+}
+
+osqp_int osqp_update_vectors(osqp_solver *h, const osqp_float *q, const osqp_float *l,
+                             const osqp_float *u) {
+  return osqp_batch_update_vectors(h, 0, q, l, u);
+}
+
+osqp_int osqp_batch_warm_start(osqp_batch *b, osqp_int i, const osqp_float *x,
+                               const osqp_float *y) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
+  const QPDesc &d = b->desc[i];
+  // NULL keeps the current iterate: take it from the last solution
+  std::vector<double> xs(d.n), ys(d.m);
+  if (x) std::memcpy(xs.data(), x, sizeof(double) * d.n);
+  else std::memcpy(xs.data(), &b->xo[d.xo], sizeof(double) * d.n);
+  if (y) std::memcpy(ys.data(), y, sizeof(double) * d.m);
+  else if (d.m) std::memcpy(ys.data(), &b->yo[d.yo], sizeof(double) * d.m);
+  for (double v : xs)
+    if (!std::isfinite(v)) return OSQP_ERR_DATA_NONFINITE;
+  for (double v : ys)
+    if (!std::isfinite(v)) return OSQP_ERR_DATA_NONFINITE;
+  auto push = [&](auto &B) -> int {
+    HIPCHK(hipMemcpyAsync((void *)(B.xws + d.xo), xs.data(), sizeof(double) * d.n,
+                          hipMemcpyHostToDevice, b->stream));
+    if (d.m)
+      HIPCHK(hipMemcpyAsync((void *)(B.yws + d.yo), ys.data(), sizeof(double) * d.m,
+                            hipMemcpyHostToDevice, b->stream));
+    const int mode = 2;
+    HIPCHK(hipMemcpyAsync((void *)&B.st[i].init_mode, &mode, sizeof(int), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return OSQP_OK;
+  };
+  return b->fp64 ? push(b->bd) : push(b->bf);
+}
+
+osqp_int osqp_warm_start(osqp_solver *h, const osqp_float *x, const osqp_float *y) {
+  return osqp_batch_warm_start(h, 0, x, y);
+}
+
+osqp_int osqp_batch_get(const osqp_batch *b, osqp_int i, osqp_float *x, osqp_float *y,
+                        osqp_info *info) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
+  const QPDesc &d = b->desc[i];
+  if (x) std::memcpy(x, &b->xo[d.xo], sizeof(double) * d.n);
+  if (y && d.m) std::memcpy(y, &b->yo[d.yo], sizeof(double) * d.m);
+  if (info) fill_info(b, i, info);
+  return OSQP_OK;
+}
+
+osqp_int osqp_get_solution(const osqp_solver *h, osqp_float *x, osqp_float *y) {
+  return osqp_batch_get(h, 0, x, y, nullptr);
+}
+
+osqp_int osqp_get_info(const osqp_solver *h, osqp_info *info) {
+  if (!info) return OSQP_ERR_NOT_SETUP;
+  return osqp_batch_get(h, 0, nullptr, nullptr, info);
+}
+
+osqp_int osqp_batch_last_kernel_ms(const osqp_batch *b, double *ms) {
+  if (!b || !ms) return OSQP_ERR_NOT_SETUP;
+  float f = 0.f;
+  if (hipEventElapsedTime(&f, b->ev0, b->ev1) != hipSuccess) return OSQP_ERR_DEVICE;
+  *ms = f;
+  return OSQP_OK;
+}
+
+osqp_int osqp_batch_count(const osqp_batch *b, osqp_int *count) {
+  if (!b || !count) return OSQP_ERR_NOT_SETUP;
+  *count = b->nq;
+  return OSQP_OK;
+}
+
+void osqp_batch_cleanup(osqp_batch *b) { destroy(b); }
+void osqp_cleanup(osqp_solver *h) { destroy(h); }
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal layout shared by the host setup code and the HIP kernels of
+// osqp_mi.  A batch of QPs is packed block-diagonally: every n-sized vector
+// of QP k lives at [xo, xo+n) of one concatenated array, every m-sized
+// vector at [yo, yo+m); every sparse matrix is CSR with per-QP local row
+// pointers (entries of QP k start at its *_nz base) and local column indices.
+#pragma once
+
+#include <cstdint>
+
+namespace osqpmi {
+
+// Per-QP descriptor (read-only on the device).
+struct QPDesc {
+  int n, m;
+  int64_t xo, yo;            // vector offsets
+  int64_t a_rp, at_rp, p_rp; // row-pointer array offsets (m+1, n+1, n+1 entries)
+  int64_t a_nz, at_nz, p_nz; // entry offsets
+  int lm, ln;                // lanes per row for passes over A rows / over P+A' rows
+  int dense_off;             // unused by the PCG path
+  int pad;
+};
+
+// Per-QP mutable state (device).
+struct QPState {
+  double c;             // cost scaling (Section 5.1)
+  double rho_bar;       // current rho-bar (Section 5.2)
+  double obj, prim_res, dual_res, eps_prim, eps_dual;
+  double prs, drs, pnorm, dnorm;   // scaled residuals / normalisers of the last check
+  double solve_ms;      // device wall time of this QP's solve
+  double polish_ms;     // device wall time of its polishing step
+  int status, iter, pcg_iter, rho_updates, polish_status;
+  int init_mode;        // 0 continue, 1 zeros, 2 warm start from xws/yws
+  int bad;              // internal failure flag (non-finite PCG scalar etc.)
+  int pad;
+};
+
+// Settings as the kernels see them.
+struct DevSettings {
+  double sigma, alpha, eps_abs, eps_rel, eps_pinf, eps_dinf, delta, time_limit;
+  double pcg_tol_frac;
+  double wall_tick_s;   // seconds per wall_clock64() tick
+  int max_iter, check_every, scaling_iters, adaptive_rho, polish, refine, pcg_max_iter;
+  int pad;
+};
+
+// Device pointers of a batch.  T is the working precision of the ADMM/PCG
+// loop; every *64 array is double.
+template <class T>
+struct Batch {
+  const QPDesc *desc;
+  QPState *st;
+  int nq;
+  const int *order;   // solve order (largest first)
+  int *counter;       // work-queue head
+  // patterns (shared by every value array of the same matrix)
+  const int *a_rp, *a_ci, *at_rp, *at_ci, *p_rp, *p_ci;
+  // unscaled data (double)
+  const double *a_raw, *at_raw, *p_raw, *q_raw, *l_raw, *u_raw;
+  // scaled data
+  T *a_v, *at_v, *p_v, *q, *l, *u, *pdiag;
+  double *a64, *at64, *p64, *q64, *l64, *u64;
+  double *D, *E, *Dinv, *Einv;
+  const unsigned char *is_eq;
+  // iterates and work vectors
+  T *rho, *rhoinv, *minv;
+  T *x, *z, *y, *xt, *zt, *r, *d, *p, *w, *t, *s;
+  double *dx, *dy;
+  const double *xws, *yws;
+  double *xo, *yo, *zo;
+  DevSettings set;
+};
+
+}  // namespace osqpmi

@@ -1,0 +1,529 @@
+// Device side of osqp_mi: per-QP routines written once against a Team
+// (workgroup or whole grid) and a working precision T (double for the FP64
+// path, float for the mixed path).  Paper references: Algorithm 1 and the
+// reduced (indirect) linear system of Section 3.1; termination and
+// infeasibility tests of Sections 3.4 and 5.1; modified Ruiz equilibration
+// (Section 5.1); rho vector and rho-bar rule (Section 5.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qp_layout.h"
+#include "team.h"
+
+namespace osqpmi {
+
+// View of one QP inside a packed batch.
+template <class T>
+struct QPView {
+  int n, m, lm, ln;
+  const int *arp, *aci, *atrp, *atci, *prp, *pci;
+  const double *araw, *atraw, *praw, *qraw, *lraw, *uraw;
+  T *av, *atv, *pv, *q, *l, *u, *pdiag;
+  double *a64, *at64, *p64, *q64, *l64, *u64;
+  double *D, *E, *Dinv, *Einv;
+  const unsigned char *iseq;
+  T *rho, *rhoinv, *minv, *x, *z, *y, *xt, *zt, *r, *d, *p, *w, *t, *s;
+  double *dx, *dy;
+  const double *xws, *yws;
+  double *xo, *yo, *zo;
+  QPState *st;
+
+  __device__ QPView(const Batch<T> &b, int k) {
+    const QPDesc &ds = b.desc[k];
+    n = ds.n; m = ds.m; lm = ds.lm; ln = ds.ln;
+    arp = b.a_rp + ds.a_rp; aci = b.a_ci + ds.a_nz;
+    atrp = b.at_rp + ds.at_rp; atci = b.at_ci + ds.at_nz;
+    prp = b.p_rp + ds.p_rp; pci = b.p_ci + ds.p_nz;
+    araw = b.a_raw + ds.a_nz; atraw = b.at_raw + ds.at_nz; praw = b.p_raw + ds.p_nz;
+    qraw = b.q_raw + ds.xo; lraw = b.l_raw + ds.yo; uraw = b.u_raw + ds.yo;
+    av = b.a_v + ds.a_nz; atv = b.at_v + ds.at_nz; pv = b.p_v + ds.p_nz;
+    q = b.q + ds.xo; l = b.l + ds.yo; u = b.u + ds.yo; pdiag = b.pdiag + ds.xo;
+    a64 = b.a64 + ds.a_nz; at64 = b.at64 + ds.at_nz; p64 = b.p64 + ds.p_nz;
+    q64 = b.q64 + ds.xo; l64 = b.l64 + ds.yo; u64 = b.u64 + ds.yo;
+    D = b.D + ds.xo; E = b.E + ds.yo; Dinv = b.Dinv + ds.xo; Einv = b.Einv + ds.yo;
+    iseq = b.is_eq + ds.yo;
+    rho = b.rho + ds.yo; rhoinv = b.rhoinv + ds.yo; minv = b.minv + ds.xo;
+    x = b.x + ds.xo; z = b.z + ds.yo; y = b.y + ds.yo; xt = b.xt + ds.xo; zt = b.zt + ds.yo;
+    r = b.r + ds.xo; d = b.d + ds.xo; p = b.p + ds.xo; w = b.w + ds.xo;
+    t = b.t + ds.yo; s = b.s + ds.yo;
+    dx = b.dx + ds.xo; dy = b.dy + ds.yo;
+    xws = b.xws + ds.xo; yws = b.yws + ds.yo;
+    xo = b.xo + ds.xo; yo = b.yo + ds.yo; zo = b.zo + ds.yo;
+    st = b.st + k;
+  }
+};
+
+// Row-group mapping: aligned groups of L lanes walk the rows of a pass.
+struct Rows {
+  int g, lane, ng, L;
+  template <class Team>
+  __device__ Rows(const Team &tm, int L_) : L(L_) {
+    g = tm.tid / L; lane = tm.tid & (L - 1); ng = tm.nt / L;
+  }
+};
+
+// Partial dot of CSR row r with x over the lanes of a group (not reduced).
+template <class A, class V, class X>
+__device__ __forceinline__ A row_partial(const int *rp, const int *ci, const V *v, int r,
+                                         int lane, int L, const X *x) {
+  A s = A(0);
+  const int e = rp[r + 1];
+  for (int k = rp[r] + lane; k < e; k += L) s += A(v[k]) * A(x[ci[k]]);
+  return s;
+}
+
+__device__ __forceinline__ double clamp_norm(double v) {
+  // reading: a column norm below 1e-4 counts as 1, above 1e4 as 1e4
+  return v < 1e-4 ? 1.0 : (v > 1e4 ? 1e4 : v);
+}
+
+// Scaled A entry; A and A' rows use this one expression so their values
+// stay bit-identical.
+__device__ __forceinline__ double scale_a(double raw, double Ei, double Dj) {
+  return (raw * Ei) * Dj;
+}
+
+// ------------------------------------------------------------------------
+// Modified Ruiz equilibration on the device (Section 5.1), from the
+// resident unscaled data; then writes the scaled data in T and in double.
+// ------------------------------------------------------------------------
+template <class T, class Team>
+__device__ void scale_qp(const Team &tm, const QPView<T> &v, const DevSettings &set) {
+  const int n = v.n, m = v.m;
+  for (int j = tm.tid; j < n; j += tm.nt) v.D[j] = 1.0;
+  for (int i = tm.tid; i < m; i += tm.nt) v.E[i] = 1.0;
+  double c = 1.0;
+  tm.sync();
+  const Rows rn(tm, v.ln), rm(tm, v.lm);
+  for (int it = 0; it < set.scaling_iters; ++it) {
+    // column infinity norms of M = [P A'; A 0] (current scaling) -> delta
+    for (int j = rn.g; j < n; j += rn.ng) {
+      double a = 0.0;
+      for (int k = v.prp[j] + rn.lane; k < v.prp[j + 1]; k += rn.L)
+        a = fmax(a, fabs(v.praw[k]) * v.D[v.pci[k]]);
+      a *= c;
+      for (int k = v.atrp[j] + rn.lane; k < v.atrp[j + 1]; k += rn.L)
+        a = fmax(a, fabs(v.atraw[k]) * v.E[v.atci[k]]);
+      a = group_max(a, rn.L) * v.D[j];
+      if (rn.lane == 0) v.dx[j] = 1.0 / sqrt(clamp_norm(a));
+    }
+    for (int i = rm.g; i < m; i += rm.ng) {
+      double a = 0.0;
+      for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L)
+        a = fmax(a, fabs(v.araw[k]) * v.D[v.aci[k]]);
+      a = group_max(a, rm.L) * v.E[i];
+      if (rm.lane == 0) v.dy[i] = 1.0 / sqrt(clamp_norm(a));
+    }
+    tm.sync();
+    for (int j = tm.tid; j < n; j += tm.nt) v.D[j] *= v.dx[j];
+    for (int i = tm.tid; i < m; i += tm.nt) v.E[i] *= v.dy[i];
+    tm.sync();
+    // cost scaling: gamma = 1 / max(mean_j ||Pbar_j||_inf, ||qbar||_inf)
+    double red[2] = {0.0, 0.0};
+    for (int j = rn.g; j < n; j += rn.ng) {
+      double a = 0.0;
+      for (int k = v.prp[j] + rn.lane; k < v.prp[j + 1]; k += rn.L)
+        a = fmax(a, fabs(v.praw[k]) * v.D[v.pci[k]]);
+      a = group_max(a, rn.L) * (c * v.D[j]);
+      if (rn.lane == 0) {
+        red[0] += a;
+        red[1] = fmax(red[1], fabs(c * v.D[j] * v.qraw[j]));
+      }
+    }
+    tm.template reduce<1, 1>(red);
+    const double s = fmax(red[0] / (double)n, red[1]);
+    // reading: gamma = 1 when P and q vanish, else clamped to [1e-4, 1e4]
+    const double gamma = s == 0.0 ? 1.0 : fmin(fmax(1.0 / s, 1e-4), 1e4);
+    c *= gamma;
+  }
+  // write the scaled problem: Pbar = c D P D, qbar = c D q, Abar = E A D,
+  // lbar = E l, ubar = E u
+  for (int j = tm.tid; j < n; j += tm.nt) {
+    const double Dj = v.D[j];
+    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) {
+      const double val = c * (v.praw[k] * Dj) * v.D[v.pci[k]];
+      v.p64[k] = val;
+      v.pv[k] = T(val);
+      if (v.pci[k] == j) v.pdiag[j] = T(val);
+    }
+    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
+      const double val = scale_a(v.atraw[k], v.E[v.atci[k]], Dj);
+      v.at64[k] = val;
+      v.atv[k] = T(val);
+    }
+    const double qq = c * Dj * v.qraw[j];
+    v.q64[j] = qq;
+    v.q[j] = T(qq);
+    v.Dinv[j] = 1.0 / Dj;
+  }
+  for (int i = tm.tid; i < m; i += tm.nt) {
+    const double Ei = v.E[i];
+    for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) {
+      const double val = scale_a(v.araw[k], Ei, v.D[v.aci[k]]);
+      v.a64[k] = val;
+      v.av[k] = T(val);
+    }
+    const double lo = v.lraw[i] * Ei, hi = v.uraw[i] * Ei;
+    v.l64[i] = lo; v.u64[i] = hi;
+    v.l[i] = T(lo); v.u[i] = T(hi);
+    v.Einv[i] = 1.0 / Ei;
+  }
+  // P without a diagonal entry in column j: pdiag = 0
+  for (int j = tm.tid; j < n; j += tm.nt) {
+    bool has = false;
+    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) has |= (v.pci[k] == j);
+    if (!has) v.pdiag[j] = T(0);
+  }
+  if (tm.tid == 0) v.st->c = c;
+  tm.sync();
+}
+
+// Rescale new vectors (q, l, u) with the stored D, E, c (Section 6).
+template <class T, class Team>
+__device__ void rescale_vectors(const Team &tm, const QPView<T> &v) {
+  const double c = v.st->c;
+  for (int j = tm.tid; j < v.n; j += tm.nt) {
+    const double qq = c * v.D[j] * v.qraw[j];
+    v.q64[j] = qq; v.q[j] = T(qq);
+  }
+  for (int i = tm.tid; i < v.m; i += tm.nt) {
+    const double lo = v.lraw[i] * v.E[i], hi = v.uraw[i] * v.E[i];
+    v.l64[i] = lo; v.u64[i] = hi; v.l[i] = T(lo); v.u[i] = T(hi);
+  }
+  tm.sync();
+}
+
+// rho_i = rho-bar (l_i != u_i) or 1e3 rho-bar (l_i == u_i), Section 5.2;
+// Jacobi preconditioner of P + sigma I + A' R A: diag(P) + sigma + sum_i rho_i A_ij^2.
+template <class T, class Team>
+__device__ void set_rho_and_precond(const Team &tm, const QPView<T> &v, double rho_bar,
+                                    double sigma) {
+  for (int i = tm.tid; i < v.m; i += tm.nt) {
+    const double r = v.iseq[i] ? 1e3 * rho_bar : rho_bar;
+    v.rho[i] = T(r);
+    v.rhoinv[i] = T(1.0 / r);
+  }
+  tm.sync();
+  const Rows rn(tm, v.ln);
+  for (int j = rn.g; j < v.n; j += rn.ng) {
+    double a = 0.0;
+    for (int k = v.atrp[j] + rn.lane; k < v.atrp[j + 1]; k += rn.L) {
+      const double e = v.at64[k];
+      a += (double)v.rho[v.atci[k]] * e * e;
+    }
+    a = group_sum(a, rn.L);
+    if (rn.lane == 0) v.minv[j] = T(1.0 / ((double)v.pdiag[j] + sigma + a));
+  }
+  tm.sync();
+}
+
+// ------------------------------------------------------------------------
+// One full solve of one QP (Algorithm 1 with the reduced-system PCG of
+// Section 3.1), then the FP64 checks, statuses and unscaled outputs.
+// ------------------------------------------------------------------------
+template <class T, class Team>
+__device__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &set) {
+  const int n = v.n, m = v.m;
+  const T sigma = T(set.sigma), alpha = T(set.alpha), one_m_alpha = T(1.0 - set.alpha);
+  const double c = v.st->c, cinv = 1.0 / c;
+  double rho_bar = v.st->rho_bar;
+  const Rows rn(tm, v.ln), rm(tm, v.lm);
+  const unsigned long long t_start = wall_clock64();
+
+  set_rho_and_precond(tm, v, rho_bar, set.sigma);
+
+  // initial iterate: continue, zeros, or the warm start of Section 6
+  const int mode = v.st->init_mode;
+  if (mode == 1) {
+    for (int j = tm.tid; j < n; j += tm.nt) { v.x[j] = T(0); v.xt[j] = T(0); }
+    for (int i = tm.tid; i < m; i += tm.nt) { v.z[i] = T(0); v.y[i] = T(0); }
+  } else if (mode == 2) {
+    for (int j = tm.tid; j < n; j += tm.nt) {
+      const T xv = T(v.Dinv[j] * v.xws[j]);
+      v.x[j] = xv; v.xt[j] = xv;
+    }
+    for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = T(c * v.Einv[i] * v.yws[i]);
+    tm.sync();
+    for (int i = rm.g; i < m; i += rm.ng) {
+      T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.x), rm.L);
+      if (rm.lane == 0) v.z[i] = a;
+    }
+  } else {
+    for (int j = tm.tid; j < n; j += tm.nt) v.xt[j] = v.x[j];
+  }
+  tm.sync();
+  // zt = A xt ; s = rho (z - zt) - y  (feeds the first right-hand side)
+  for (int i = rm.g; i < m; i += rm.ng) {
+    T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.xt), rm.L);
+    if (rm.lane == 0) {
+      v.zt[i] = a;
+      v.s[i] = v.rho[i] * (v.z[i] - a) - v.y[i];
+    }
+  }
+  tm.sync();
+
+  int k = 0, status = 6 /* unsolved */, pcg_total = 0, rho_updates = 0;
+  bool have_check = false;
+  double prs = 0.0, drs = 0.0, pnorm = 0.0, dnorm = 0.0, bnorm = -1.0;
+  double res_prim = 0.0, res_dual = 0.0, eps_prim = 0.0, eps_dual = 0.0;
+  const double floor_rel = sizeof(T) == 4 ? 1e-6 : 1e-12;
+  int bad = 0;
+
+  while (true) {
+    // --- PCG start: r = b - K xt with b = sigma x - q + A'(rho z - y)
+    //     (Section 3.1, indirect method), K = P + sigma I + A' R A, using
+    //     A xt = zt:  r = sigma (x - xt) - q - P xt + A' s
+    double red[2];
+    red[0] = 0.0; red[1] = 0.0;
+    for (int j = rn.g; j < n; j += rn.ng) {
+      T a = row_partial<T>(v.atrp, v.atci, v.atv, j, rn.lane, rn.L, v.s) -
+            row_partial<T>(v.prp, v.pci, v.pv, j, rn.lane, rn.L, v.xt);
+      a = group_sum(a, rn.L);
+      if (rn.lane == 0) {
+        const T rj = sigma * (v.x[j] - v.xt[j]) - v.q[j] + a;
+        const T dj = v.minv[j] * rj;
+        v.r[j] = rj; v.d[j] = dj; v.p[j] = dj;
+        red[0] += double(rj * dj);
+        red[1] = fmax(red[1], fabs(double(rj)));
+      }
+    }
+    tm.template reduce<1, 1>(red);
+    double rz = red[0], rinf = red[1];
+    if (bnorm < 0.0) bnorm = rinf;
+    // inner tolerance (reading): kappa * min(prim, dual residual) of the last
+    // check, floored relative to the dual normaliser; 1e-3 of the first
+    // residual before the first check
+    double tol = have_check
+                     ? fmax(set.pcg_tol_frac * fmin(prs, drs), floor_rel * fmax(dnorm, 1e-30))
+                     : 1e-3 * bnorm;
+    int it = 0;
+    while (rinf > tol && it < set.pcg_max_iter) {
+      // t = R A p
+      for (int i = rm.g; i < m; i += rm.ng) {
+        T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.p), rm.L);
+        if (rm.lane == 0) v.t[i] = v.rho[i] * a;
+      }
+      tm.sync();
+      // w = P p + sigma p + A' t ; p'w
+      red[0] = 0.0;
+      for (int j = rn.g; j < n; j += rn.ng) {
+        T a = row_partial<T>(v.prp, v.pci, v.pv, j, rn.lane, rn.L, v.p) +
+              row_partial<T>(v.atrp, v.atci, v.atv, j, rn.lane, rn.L, v.t);
+        a = group_sum(a, rn.L);
+        if (rn.lane == 0) {
+          const T pj = v.p[j];
+          const T wj = a + sigma * pj;
+          v.w[j] = wj;
+          red[0] += double(pj * wj);
+        }
+      }
+      tm.template reduce<1, 0>(red);
+      const double pw = red[0];
+      if (!(pw > 0.0) || !isfinite(pw)) { bad |= 1; break; }
+      const T a_step = T(rz / pw);
+      red[0] = 0.0; red[1] = 0.0;
+      for (int j = tm.tid; j < n; j += tm.nt) {
+        v.xt[j] += a_step * v.p[j];
+        const T rj = v.r[j] - a_step * v.w[j];
+        const T dj = v.minv[j] * rj;
+        v.r[j] = rj; v.d[j] = dj;
+        red[0] += double(rj * dj);
+        red[1] = fmax(red[1], fabs(double(rj)));
+      }
+      tm.template reduce<1, 1>(red);
+      const T beta = T(red[0] / rz);
+      rz = red[0];
+      rinf = red[1];
+      for (int j = tm.tid; j < n; j += tm.nt) v.p[j] = v.d[j] + beta * v.p[j];
+      tm.sync();
+      ++it;
+      if (!(rz > 0.0)) break;
+    }
+    pcg_total += it;
+    ++k;
+    const bool do_check = (set.check_every > 0 && k % set.check_every == 0) || k >= set.max_iter;
+    // --- Algorithm 1 updates: x relaxed; v = alpha zt + (1-alpha) z + y/rho;
+    //     z = Pi(v); y = rho (v - z)  (v-form of Section 3.3)
+    for (int j = tm.tid; j < n; j += tm.nt) {
+      const T xn = alpha * v.xt[j] + one_m_alpha * v.x[j];
+      if (do_check) v.dx[j] = double(xn) - double(v.x[j]);
+      v.x[j] = xn;
+    }
+    for (int i = rm.g; i < m; i += rm.ng) {
+      T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.xt), rm.L);
+      if (rm.lane == 0) {
+        const T zi = v.z[i], yi = v.y[i], ri = v.rho[i];
+        const T vv = alpha * a + one_m_alpha * zi + v.rhoinv[i] * yi;
+        const T zn = fmin(fmax(vv, v.l[i]), v.u[i]);
+        const T yn = ri * (vv - zn);
+        if (do_check) v.dy[i] = double(yn) - double(yi);
+        v.zt[i] = a;
+        v.z[i] = zn;
+        v.y[i] = yn;
+        v.s[i] = ri * (zn - a) - yn;
+      }
+    }
+    tm.sync();
+    if (!do_check) continue;
+
+    // --- FP64 termination check (Sections 3.4, 5.1): unscaled residuals
+    //     and tolerances, then the infeasibility tests on dy, dx.
+    //  sums : [0] u'dy+ + l'dy-, [1] q'dx
+    //  maxes: [2] |E^-1(Ax-z)| [3] |E^-1 Ax| [4] |E^-1 z| [5] |Ax-z| [6] |Ax| [7] |z|
+    //         [8] |D^-1(Px+q+A'y)| [9] |D^-1 Px| [10] |D^-1 A'y| [11] |D^-1 q|
+    //         [12] |Px+q+A'y| [13] |Px| [14] |A'y| [15] |q|
+    //         [16] |E dy| [17] |D^-1 A'dy| [18] inf-bound hit
+    //         [19] |D dx| [20] |D^-1 P dx| [21] both-finite |E^-1 A dx|
+    //         [22] lower-only -(E^-1 A dx) [23] upper-only (E^-1 A dx) [24] elapsed s
+    double chk[25];
+#pragma unroll
+    for (int kk = 0; kk < 25; ++kk) chk[kk] = 0.0;
+    for (int i = rm.g; i < m; i += rm.ng) {
+      double ax = 0.0, adx = 0.0;
+      for (int kq = v.arp[i] + rm.lane; kq < v.arp[i + 1]; kq += rm.L) {
+        const double a = v.a64[kq];
+        const int cj = v.aci[kq];
+        ax += a * double(v.x[cj]);
+        adx += a * v.dx[cj];
+      }
+      ax = group_sum(ax, rm.L);
+      adx = group_sum(adx, rm.L);
+      if (rm.lane == 0) {
+        const double zi = double(v.z[i]), ei = v.Einv[i];
+        chk[2] = fmax(chk[2], fabs(ei * (ax - zi)));
+        chk[3] = fmax(chk[3], fabs(ei * ax));
+        chk[4] = fmax(chk[4], fabs(ei * zi));
+        chk[5] = fmax(chk[5], fabs(ax - zi));
+        chk[6] = fmax(chk[6], fabs(ax));
+        chk[7] = fmax(chk[7], fabs(zi));
+        const double dyi = v.dy[i];
+        chk[16] = fmax(chk[16], fabs(v.E[i] * dyi));
+        // reading: only dy_i > 0 meets u_i and only dy_i < 0 meets l_i; an
+        // infinite bound met this way fails the test
+        if (dyi > 0.0) {
+          if (isinf(v.u64[i])) chk[18] = 1.0; else chk[0] += v.u64[i] * dyi;
+        } else if (dyi < 0.0) {
+          if (isinf(v.l64[i])) chk[18] = 1.0; else chk[0] += v.l64[i] * dyi;
+        }
+        const double wv = ei * adx;
+        const bool lf = !isinf(v.l64[i]), uf = !isinf(v.u64[i]);
+        if (lf && uf) chk[21] = fmax(chk[21], fabs(wv));
+        else if (lf) chk[22] = fmax(chk[22], -wv);
+        else if (uf) chk[23] = fmax(chk[23], wv);
+      }
+    }
+    for (int j = rn.g; j < n; j += rn.ng) {
+      double px = 0.0, pdx = 0.0, aty = 0.0, atdy = 0.0;
+      for (int kq = v.prp[j] + rn.lane; kq < v.prp[j + 1]; kq += rn.L) {
+        const double a = v.p64[kq];
+        const int cj = v.pci[kq];
+        px += a * double(v.x[cj]);
+        pdx += a * v.dx[cj];
+      }
+      for (int kq = v.atrp[j] + rn.lane; kq < v.atrp[j + 1]; kq += rn.L) {
+        const double a = v.at64[kq];
+        const int ci = v.atci[kq];
+        aty += a * double(v.y[ci]);
+        atdy += a * v.dy[ci];
+      }
+      px = group_sum(px, rn.L); pdx = group_sum(pdx, rn.L);
+      aty = group_sum(aty, rn.L); atdy = group_sum(atdy, rn.L);
+      if (rn.lane == 0) {
+        const double qj = v.q64[j], di = v.Dinv[j];
+        const double rd = px + qj + aty;
+        chk[8] = fmax(chk[8], fabs(di * rd));
+        chk[9] = fmax(chk[9], fabs(di * px));
+        chk[10] = fmax(chk[10], fabs(di * aty));
+        chk[11] = fmax(chk[11], fabs(di * qj));
+        chk[12] = fmax(chk[12], fabs(rd));
+        chk[13] = fmax(chk[13], fabs(px));
+        chk[14] = fmax(chk[14], fabs(aty));
+        chk[15] = fmax(chk[15], fabs(qj));
+        chk[17] = fmax(chk[17], fabs(di * atdy));
+        const double dxj = v.dx[j];
+        chk[19] = fmax(chk[19], fabs(v.D[j] * dxj));
+        chk[20] = fmax(chk[20], fabs(di * pdx));
+        chk[1] += qj * dxj;
+      }
+    }
+    if (tm.tid == 0) chk[24] = double(wall_clock64() - t_start) * set.wall_tick_s;
+    tm.template reduce<2, 23>(chk);
+    res_prim = chk[2];
+    eps_prim = set.eps_abs + set.eps_rel * fmax(chk[3], chk[4]);
+    res_dual = cinv * chk[8];
+    eps_dual = set.eps_abs + set.eps_rel * cinv * fmax(chk[9], fmax(chk[10], chk[11]));
+    prs = chk[5]; pnorm = fmax(chk[6], chk[7]);
+    drs = chk[12]; dnorm = fmax(chk[13], fmax(chk[14], chk[15]));
+    have_check = true;
+    if (res_prim <= eps_prim && res_dual <= eps_dual) { status = 1; break; }
+    // primal infeasibility (Section 5.1, strict-sign reading)
+    {
+      const double ndy = chk[16];
+      if (ndy > 0.0 && chk[18] == 0.0 && chk[0] < -set.eps_pinf * ndy &&
+          chk[17] <= set.eps_pinf * ndy) { status = 2; break; }
+    }
+    // dual infeasibility (Section 5.1)
+    {
+      const double ndx = chk[19], tl = set.eps_dinf * ndx;
+      if (ndx > 0.0 && chk[1] < -c * tl && chk[20] <= c * tl && chk[21] <= tl &&
+          chk[22] <= tl && chk[23] <= tl) { status = 3; break; }
+    }
+    if (set.time_limit > 0.0 && chk[24] >= set.time_limit) { status = 5; break; }
+    if (k >= set.max_iter) { status = 4; break; }
+    if (bad) { status = 6; break; }
+    // rho-bar rule (Section 5.2), scaled quantities; readings: skip on zero
+    // normalisers, clamp to [1e-6, 1e6], apply at a 5x change
+    if (set.adaptive_rho && pnorm > 0.0 && dnorm > 0.0 && drs > 0.0) {
+      double rnew = rho_bar * sqrt((prs / pnorm) / (drs / dnorm));
+      rnew = fmin(fmax(rnew, 1e-6), 1e6);
+      if (rnew > 5.0 * rho_bar || rnew < rho_bar / 5.0) {
+        rho_bar = rnew;
+        ++rho_updates;
+        set_rho_and_precond(tm, v, rho_bar, set.sigma);
+        for (int i = tm.tid; i < m; i += tm.nt)
+          v.s[i] = v.rho[i] * (v.z[i] - v.zt[i]) - v.y[i];
+        tm.sync();
+      }
+    }
+  }
+
+  // --- unscale (Section 5.1) and objective on the scaled data divided by c
+  double red[1];
+  red[0] = 0.0;
+  for (int j = rn.g; j < n; j += rn.ng) {
+    double px = 0.0;
+    for (int kq = v.prp[j] + rn.lane; kq < v.prp[j + 1]; kq += rn.L)
+      px += v.p64[kq] * double(v.x[v.pci[kq]]);
+    px = group_sum(px, rn.L);
+    if (rn.lane == 0) {
+      const double xj = double(v.x[j]);
+      red[0] += 0.5 * xj * px + v.q64[j] * xj;
+      v.xo[j] = v.D[j] * (status == 3 ? v.dx[j] : xj);
+    }
+  }
+  for (int i = tm.tid; i < m; i += tm.nt) {
+    v.yo[i] = cinv * v.E[i] * (status == 2 ? v.dy[i] : double(v.y[i]));
+    v.zo[i] = v.Einv[i] * double(v.z[i]);
+  }
+  tm.template reduce<1, 0>(red);
+  if (tm.tid == 0) {
+    QPState &S = *v.st;
+    S.status = status;
+    S.iter = k;
+    S.pcg_iter = pcg_total;
+    S.rho_updates = rho_updates;
+    S.rho_bar = rho_bar;
+    S.prim_res = res_prim; S.dual_res = res_dual;
+    S.eps_prim = eps_prim; S.eps_dual = eps_dual;
+    S.prs = prs; S.drs = drs; S.pnorm = pnorm; S.dnorm = dnorm;
+    S.obj = status == 2 ? INFINITY : (status == 3 ? -INFINITY : cinv * red[0]);
+    S.polish_status = 0;
+    S.init_mode = 0;
+    S.bad = bad;
+    S.solve_ms = double(wall_clock64() - t_start) * set.wall_tick_s * 1e3;
+  }
+  tm.sync();
+}
+
+}  // namespace osqpmi

@@ -1,0 +1,226 @@
+"""GPU parity against the FP64 CPU oracle, through the C ABI (the ctypes
+binding only marshals arguments).  Statuses must match exactly; solved
+results must pass the Section 3.4 test recomputed in FP64 on the original
+data, and the objective must agree to 1e-3 relative."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import qpgen
+from qpgen import QP
+from tests import gpu_common as gc
+from tests import qpcheck
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_1711_08013_amd as pm
+    assert pm.device_count() > 0, "no HIP device"
+    return pm
+
+
+def _solve_batch(pm, qps, **settings):
+    b = pm.Batch(qps, **settings)
+    b.solve()
+    res = [b.get(i) for i in range(len(qps))]
+    b.close()
+    return res
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_random_qp_single_instance(pm, precision):
+    """Workload 1 (random QP, n=50, m=500) as single instances."""
+    rows = []
+    for i in range(3):
+        qp = qpgen.config_instance(1, i)
+        print(f"random_qp seed [1,{i}] {precision}", flush=True)
+        x, y, info = pm.solve(qp, precision=precision)
+        rows.append(gc.compare(qp, x, y, info, oracle.solve(qp)))
+    errs = gc.summarize(rows, f"random_qp single {precision}")
+    assert max(errs) <= gc.OBJ_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_random_qp_100_seeds(pm, precision):
+    """Workload 1 over seeds [1,0..99], solved as one batch."""
+    qps = [qpgen.config_instance(1, i) for i in range(100)]
+    print(f"random_qp 100 seeds {precision}", flush=True)
+    res = _solve_batch(pm, qps, precision=precision)
+    rows = [gc.compare(qp, *r, oracle.solve(qp)) for qp, r in zip(qps, res)]
+    gc.summarize(rows, f"random_qp x100 {precision}")
+    gc.assert_obj_parity(rows, f"random_qp x100 {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_mpc_batch(pm, precision):
+    """Workload 3 generator (MPC, T in 5..20), 96 instances, 24 checked."""
+    qps = [qpgen.config_instance(3, i) for i in range(96)]
+    print(f"mpc x96 {precision}", flush=True)
+    res = _solve_batch(pm, qps, precision=precision)
+    rows = [gc.compare(qps[i], *res[i], oracle.solve(qps[i])) for i in range(0, 96, 4)]
+    gc.summarize(rows, f"mpc x96 {precision}")
+    gc.assert_obj_parity(rows, f"mpc x96 {precision}")
+
+
+def test_portfolio_batch_status_and_residuals(pm):
+    """Workload 4 generator (portfolio), 12 instances with n in 100..800:
+    status and eps-scaled residuals (objective parity is checked with polish)."""
+    qps = [qpgen.config_instance(4, i, n_range=(100, 800)) for i in range(12)]
+    print("portfolio x12 fp32", flush=True)
+    res = _solve_batch(pm, qps, precision="fp32")
+    rows = [gc.compare(qps[i], *res[i], oracle.solve(qps[i])) for i in range(12)]
+    gc.summarize(rows, "portfolio x12 fp32 (unpolished)")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_lasso_small(pm, precision):
+    qp = qpgen.lasso(qpgen.rng_for(9, 5), 50, 500, density=0.15)
+    print(f"lasso 50x500 {precision}", flush=True)
+    x, y, info = pm.solve(qp, precision=precision)
+    row = gc.compare(qp, x, y, info, oracle.solve(qp))
+    assert row["obj_err"] <= gc.OBJ_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_primal_infeasible(pm, precision):
+    A = sp.csr_matrix(np.array([[1.0, 0.0], [1.0, 0.0], [0.0, 1.0]]))
+    qp = QP(sp.csr_matrix(np.eye(2)), np.zeros(2), A, np.array([1.0, -np.inf, -1.0]),
+            np.array([np.inf, 0.0, 1.0]))
+    print(f"primal infeasible {precision}", flush=True)
+    x, y, info = pm.solve(qp, precision=precision)
+    assert info["status_name"] == "primal_infeasible"
+    assert np.max(np.abs(A.T @ y)) <= 1e-3 * np.max(np.abs(y))
+    supp = sum(qp.u[i] * y[i] for i in range(3) if y[i] > 0) + \
+        sum(qp.l[i] * y[i] for i in range(3) if y[i] < 0)
+    assert supp < 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_dual_infeasible(pm, precision):
+    n = 5
+    qp = qpgen.box_qp(np.zeros(n), -np.ones(n), np.zeros(n), np.inf * np.ones(n))
+    print(f"dual infeasible {precision}", flush=True)
+    x, y, info = pm.solve(qp, precision=precision)
+    assert info["status_name"] == "dual_infeasible"
+    assert qp.q @ x < 0
+    assert np.all(qp.A @ x >= -1e-3 * np.max(np.abs(x)))
+
+
+def test_max_iter_status(pm):
+    qp = qpgen.config_instance(1, 0)
+    x, y, info = pm.solve(qp, max_iter=1)
+    assert info["status_name"] == "max_iter_reached" and info["iter"] == 1
+
+
+def test_warm_start_from_optimum(pm):
+    """Section 6: warm start at the oracle's solution solves at the first check."""
+    qp = qpgen.config_instance(1, 3)
+    r = oracle.solve(qp)
+    s = pm.Solver(qp, precision="fp64")
+    s.warm_start(r.x, r.y)
+    s.solve()
+    x, y, info = s.result()
+    s.close()
+    assert info["status_name"] == "solved" and info["iter"] <= 25
+
+
+def test_update_vectors_matches_fresh_setup(pm):
+    """Section 6: new l, u (MPC initial state) through osqp_update_vectors
+    give the oracle's solution of the updated problem."""
+    rng = qpgen.rng_for(3, 500)
+    plant = qpgen.mpc_plant(rng)
+    qp0 = qpgen.mpc(rng, T=10, plant=plant)
+    qp1 = qpgen.mpc(rng, T=10, plant=plant)   # same matrices, new x_init
+    s = pm.Solver(qp0, precision="fp32")
+    s.solve()
+    s.update_vectors(l=qp1.l, u=qp1.u)
+    s.solve()
+    x, y, info = s.result()
+    s.close()
+    gc.compare(qp1, x, y, info, oracle.solve(qp1))
+
+
+def test_deterministic_and_alone_equals_mix(pm):
+    """The same QP gives bitwise-identical results when solved twice, and
+    alone or inside a batch of other QPs (one QP per workgroup, fixed
+    reduction order)."""
+    target = qpgen.config_instance(3, 7)
+    others = [qpgen.config_instance(3, i) for i in range(20, 40)]
+    xa, ya, ia = _solve_batch(pm, [target], precision="fp32")[0]
+    xb, yb, ib = _solve_batch(pm, [target], precision="fp32")[0]
+    mix = _solve_batch(pm, others[:10] + [target] + others[10:], precision="fp32")
+    xm, ym, im = mix[10]
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    assert np.array_equal(xa, xm) and np.array_equal(ya, ym)
+    assert ia["iter"] == im["iter"] and ia["status"] == im["status"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_lasso_full_size_grid_team(pm, precision):
+    """Workload 2 (Lasso, 10000 x 2000 at 5%): one QP on the whole grid."""
+    qp = qpgen.config_instance(2, 0)
+    print(f"lasso full {precision}", flush=True)
+    x, y, info = pm.solve(qp, precision=precision)
+    ref = oracle.solve(qp)
+    row = gc.compare(qp, x, y, info, ref)
+    print(f"lasso full {precision}: it={info['iter']} pcg={info['pcg_iter']} "
+          f"obj_err={row['obj_err']:.2e}", flush=True)
+    assert row["obj_err"] <= gc.OBJ_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_polish_matches_brute_force(pm, precision):
+    """Section 4 on tiny QPs: the device's FP64 polish (dense condensed
+    Cholesky + iterative refinement) reproduces the enumerated optimum."""
+    from tests.test_oracle_pins import _tiny_random
+    qps = [_tiny_random(s) for s in range(40)]
+    print(f"polish tiny x40 {precision}", flush=True)
+    res = _solve_batch(pm, qps, precision=precision, polish=1)
+    ok = 0
+    for qp, (x, y, info) in zip(qps, res):
+        x_bf, _, f_bf = qpcheck.brute_force(qp)
+        assert info["status_name"] == "solved"
+        if info["polish_status"] == 1:
+            ok += 1
+            assert np.allclose(x, x_bf, atol=1e-7), qp.name
+            assert abs(info["obj_val"] - f_bf) <= 1e-8 * max(1.0, abs(f_bf)), qp.name
+    print(f"polish accepted on {ok} of 40", flush=True)
+    assert ok >= 30
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_random_qp_100_seeds_polished(pm, precision):
+    """Workload 1 with polishing on both sides: objectives agree to 1e-3 on
+    every seed (to 1e-7 where both polishes are accepted)."""
+    qps = [qpgen.config_instance(1, i) for i in range(100)]
+    res = _solve_batch(pm, qps, precision=precision, polish=1)
+    rows, both = [], 0
+    for qp, (x, y, info) in zip(qps, res):
+        ref = oracle.solve(qp, polish=1)
+        rows.append(gc.compare(qp, x, y, info, ref))
+        if info["polish_status"] == 1 and ref.polish_status == 1:
+            both += 1
+            assert rows[-1]["obj_err"] <= 1e-7
+    errs = gc.summarize(rows, f"random_qp x100 polished {precision}")
+    print(f"both polished: {both} of 100", flush=True)
+    assert max(errs) <= gc.OBJ_TOL
+
+
+def test_portfolio_polished_parity(pm):
+    """Workload 4 generator with FP64 polish on the FP32 path: objective
+    parity against the polished oracle."""
+    qps = [qpgen.config_instance(4, i, n_range=(100, 800)) for i in range(12)]
+    res = _solve_batch(pm, qps, precision="fp32", polish=1)
+    rows = []
+    for qp, (x, y, info) in zip(qps, res):
+        ref = oracle.solve(qp, polish=1)
+        rows.append(gc.compare(qp, x, y, info, ref))
+        print(f"  {qp.name}: polish gpu={info['polish_status']} oracle={ref.polish_status} "
+              f"err={rows[-1]['obj_err']:.2e}", flush=True)
+    errs = gc.summarize(rows, "portfolio x12 polished")
+    assert max(errs) <= gc.OBJ_TOL
