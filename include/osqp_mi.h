@@ -127,6 +127,12 @@ const char *osqp_error_string(osqp_int code);
 /* Number of visible HIP devices (0 when none), for callers that must gate. */
 osqp_int osqp_device_count(void);
 
+/* Properties of the current device the library sizes its launches by: compute
+ * units, LDS bytes a workgroup may use, LDS bytes per CU, and the rate of the
+ * device wall clock in kHz.  Any pointer may be NULL. */
+osqp_int osqp_device_info(osqp_int *cu_count, osqp_int *lds_per_block, osqp_int *lds_per_cu,
+                          osqp_int *wall_khz);
+
 /* ---- single QP (Sections 3-5) ------------------------------------------ */
 
 /* Validate and copy one QP to the device, build P's full symmetric pattern
@@ -185,6 +191,12 @@ osqp_int osqp_batch_get(const osqp_batch *b, osqp_int i, osqp_float *x, osqp_flo
  * the batch's stream). */
 osqp_int osqp_batch_last_kernel_ms(const osqp_batch *b, double *ms);
 osqp_int osqp_batch_count(const osqp_batch *b, osqp_int *count);
+/* Copy the dense Cholesky factor L of problem i's reduced matrix
+ * P + sigma I + A'RA (scaled data, current rho; Section 3.1 indirect form)
+ * to L_out as n*n row-major doubles, lower triangle (upper part zero).
+ * Returns OSQP_ERR_NOT_SETUP when problem i does not use the dense path or
+ * has no valid factor yet.  For checking and diagnostics. */
+osqp_int osqp_batch_get_factor(const osqp_batch *b, osqp_int i, osqp_float *L_out);
 void osqp_batch_cleanup(osqp_batch *b);
 
 #ifdef __cplusplus

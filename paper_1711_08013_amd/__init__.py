@@ -26,12 +26,14 @@ LINSYS = {"auto": 0, "pcg": 1, "dense": 2}
 
 # every function the header declares (the CPU tests check the exports)
 EXPORTS = [
-    "osqp_set_default_settings", "osqp_error_string", "osqp_device_count", "osqp_setup",
+    "osqp_set_default_settings", "osqp_error_string", "osqp_device_count",
+    "osqp_device_info", "osqp_setup",
     "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_get_solution",
     "osqp_get_info", "osqp_cleanup", "osqp_batch_setup", "osqp_batch_solve",
     "osqp_batch_solve_async", "osqp_batch_sync", "osqp_batch_reset",
     "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_get",
-    "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_cleanup",
+    "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_get_factor",
+    "osqp_batch_cleanup",
 ]
 
 
@@ -96,6 +98,12 @@ def lib() -> ctypes.CDLL:
 
 def device_count() -> int:
     return int(lib().osqp_device_count())
+
+
+def device_info() -> dict:
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    _check(lib().osqp_device_info(*[ctypes.byref(x) for x in v]), "osqp_device_info")
+    return dict(zip(("cu_count", "lds_per_block", "lds_per_cu", "wall_khz"), (x.value for x in v)))
 
 
 def default_settings() -> dict:
@@ -219,6 +227,13 @@ class Batch:
         _check(lib().osqp_batch_get(self._h, i, _ptr(x), _ptr(y), ctypes.byref(info)),
                "osqp_batch_get")
         return x, y[:m], _info_dict(info)
+
+    def factor(self, i: int):
+        """Dense Cholesky factor L (n x n, lower) of problem i's reduced matrix."""
+        n, _ = self.sizes[i]
+        L = np.zeros((n, n))
+        _check(lib().osqp_batch_get_factor(self._h, i, _ptr(L)), "osqp_batch_get_factor")
+        return L
 
     def last_kernel_ms(self) -> float:
         ms = ctypes.c_double(0.0)

@@ -21,6 +21,9 @@ namespace {
 
 constexpr double kInfBound = 1e30;
 constexpr int kPolishMaxN = 3000;   // largest n polished with a dense condensed system
+constexpr int kDenseMaxN = 4096;    // largest n that may use the dense preconditioner
+constexpr int kDenseAutoN = 2500;   // largest n given the dense preconditioner by default
+constexpr double kDenseBudget = 48e9;   // bytes of dense factors per batch
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -125,6 +128,9 @@ struct osqp_batch {
   std::vector<QPDesc> desc;
   std::vector<int> small_list, big_list;   // workgroup-team QPs / grid-team QPs
   int64_t sum_n = 0, sum_m = 0, nnz_a = 0, nnz_p = 0;
+  int64_t dense_total = 0, mr_total = 0, dws_stride = 0;
+  int dws_slots = 0;
+  std::vector<int> mrows;
   // host staging of the inputs that change through the parametric API
   std::vector<double> q_raw, l_raw, u_raw;
   std::vector<unsigned char> is_eq;
@@ -239,6 +245,10 @@ void fill_batch_ptrs(Batch<T> &B, osqp_batch *b, Arena &ar, bool alias64) {
   B.xo = ar.take<double>(sn);
   B.yo = ar.take<double>(sm);
   B.zo = ar.take<double>(sm);
+  B.mrows = ar.take<int>(std::max<int64_t>(1, b->mr_total));
+  B.dmat = b->dense_total > 0 ? ar.take<T>(b->dense_total) : nullptr;
+  B.dws = b->dense_total > 0 ? ar.take<T>((size_t)b->dws_stride * b->dws_slots) : nullptr;
+  B.dws_stride = b->dws_stride;
 }
 
 template <class T>
@@ -248,6 +258,26 @@ size_t arena_bytes_for(osqp_batch *b, bool alias64) {
   Batch<T> B{};
   fill_batch_ptrs(B, b, probe, alias64);
   return probe.used + 4096;
+}
+
+// Refuse to run a kernel whose static LDS exceeds what the device grants a
+// workgroup (the launch would otherwise read past its allocation).
+int check_lds(const void *fn, size_t limit) {
+  hipFuncAttributes attr;
+  if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return OSQP_ERR_DEVICE;
+  return attr.sharedSizeBytes <= limit ? OSQP_OK : OSQP_ERR_DEVICE;
+}
+
+template <class T>
+int check_kernels_lds(size_t limit) {
+  int rc = OSQP_OK;
+  const void *fns[] = {(const void *)solve_wg_kernel<T>, (const void *)scale_wg_kernel<T>,
+                       (const void *)polish_wg_kernel<T>, (const void *)solve_grid_kernel<T>,
+                       (const void *)scale_grid_kernel<T>,
+                       (const void *)rescale_vectors_wg_kernel<T>};
+  for (const void *f : fns)
+    if ((rc = check_lds(f, limit)) != OSQP_OK) return rc;
+  return rc;
 }
 
 template <class T>
@@ -373,6 +403,37 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     return OSQP_ERR_DEVICE;
   }
 
+  // ---- launch geometry ------------------------------------------------------
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { destroy(b); return OSQP_ERR_DEVICE; }
+  {
+    const int lrc = b->fp64 ? check_kernels_lds<double>(prop.sharedMemPerBlock)
+                            : check_kernels_lds<float>(prop.sharedMemPerBlock);
+    if (lrc) { destroy(b); return lrc; }
+  }
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess ||
+      wall_khz <= 0)
+    wall_khz = 100000;
+  b->wall_tick_s = 1.0 / (1e3 * wall_khz);
+  b->block = s.block_size ? s.block_size : 256;
+  int per_cu = 1;
+  if (b->fp64)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<double>, b->block, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<float>, b->block, 0);
+  per_cu = std::max(1, per_cu);
+  b->grid_wg = prop.multiProcessorCount * per_cu;
+  b->coop_block = 256;
+  int coop_per_cu = 1;
+  if (b->fp64)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&coop_per_cu, solve_grid_kernel<double>,
+                                                       b->coop_block, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&coop_per_cu, solve_grid_kernel<float>,
+                                                       b->coop_block, 0);
+  // one workgroup per CU keeps the grid barrier cheap; never more than resident
+  b->grid_coop = prop.multiProcessorCount * std::min(1, std::max(1, coop_per_cu));
   // ---- sizes, offsets, patterns (host) ------------------------------------
   b->desc.resize(count);
   std::vector<int64_t> pfull_nnz(count);
@@ -407,6 +468,50 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
   }
   std::stable_sort(b->small_list.begin(), b->small_list.end(),
                    [&](int a, int c) { return cost[a] > cost[c]; });
+  // rows of A with at least two entries (rank-k part of A'RA), all QPs
+  for (int k = 0; k < count; ++k) {
+    const osqp_problem &p = probs[k];
+    b->desc[k].mr_off = (int64_t)b->mrows.size();
+    for (int i = 0; i < p.m; ++i)
+      if (p.A.indptr[i + 1] - p.A.indptr[i] >= 2) b->mrows.push_back(i);
+    b->desc[k].mr_cnt = (int)((int64_t)b->mrows.size() - b->desc[k].mr_off);
+  }
+  b->mr_total = (int64_t)b->mrows.size();
+  // dense preconditioner for workgroup-team QPs up to a size and a memory budget
+  {
+    const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
+    std::vector<int> cand;
+    for (int k : b->small_list) {
+      const int n = probs[k].n;
+      const bool want = (s.linsys == OSQP_LINSYS_DENSE && n <= kDenseMaxN) ||
+                        (s.linsys == OSQP_LINSYS_AUTO && n <= kDenseAutoN);
+      b->desc[k].dense = 0;
+      b->desc[k].dld = 0;
+      b->desc[k].dense_off = 0;
+      if (want) cand.push_back(k);
+    }
+    std::stable_sort(cand.begin(), cand.end(),
+                     [&](int a, int c) { return probs[a].n < probs[c].n; });
+    double bytes = 0.0;
+    int nmax = 0, rmax = 0;
+    for (int k : cand) {
+      const int n = probs[k].n, ld = (n + 7) & ~7;
+      const double need = (double)n * ld * tsz;
+      if (bytes + need > kDenseBudget) break;
+      bytes += need;
+      QPDesc &d = b->desc[k];
+      d.dense = 1;
+      d.dld = ld;
+      d.dense_off = b->dense_total;
+      b->dense_total += (int64_t)n * ld;
+      nmax = std::max(nmax, n);
+      rmax = std::max(rmax, d.mr_cnt);
+    }
+    if (b->dense_total > 0) {
+      b->dws_stride = ((int64_t)nmax * rmax + 63) & ~int64_t(63);
+      b->dws_slots = b->grid_wg;
+    }
+  }
 
   const bool alias = b->fp64;
   b->arena_bytes = b->fp64 ? arena_bytes_for<double>(b, true) : arena_bytes_for<float>(b, false);
@@ -523,37 +628,12 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     ok &= up((void *)B.l_raw, b->l_raw.data(), sizeof(double) * sm);
     ok &= up((void *)B.u_raw, b->u_raw.data(), sizeof(double) * sm);
     ok &= up((void *)B.is_eq, b->is_eq.data(), sm);
+    ok &= up((void *)B.mrows, b->mrows.data(), sizeof(int) * b->mrows.size());
     return ok;
   };
   bool ok = b->fp64 ? upload(b->bd) : upload(b->bf);
   if (!ok) { destroy(b); return OSQP_ERR_DEVICE; }
 
-  // ---- launch geometry ------------------------------------------------------
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { destroy(b); return OSQP_ERR_DEVICE; }
-  int wall_khz = 0;
-  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess ||
-      wall_khz <= 0)
-    wall_khz = 100000;
-  b->wall_tick_s = 1.0 / (1e3 * wall_khz);
-  b->block = s.block_size ? s.block_size : 256;
-  int per_cu = 1;
-  if (b->fp64)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<double>, b->block, 0);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<float>, b->block, 0);
-  per_cu = std::max(1, per_cu);
-  b->grid_wg = prop.multiProcessorCount * per_cu;
-  b->coop_block = 256;
-  int coop_per_cu = 1;
-  if (b->fp64)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&coop_per_cu, solve_grid_kernel<double>,
-                                                       b->coop_block, 0);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&coop_per_cu, solve_grid_kernel<float>,
-                                                       b->coop_block, 0);
-  // one workgroup per CU keeps the grid barrier cheap; never more than resident
-  b->grid_coop = prop.multiProcessorCount * std::min(1, std::max(1, coop_per_cu));
   if (!b->big_list.empty()) {
     if (hipMalloc(&b->d_partials, sizeof(double) * 2 * kRedSlots * b->grid_coop) != hipSuccess ||
         hipMalloc(&b->d_bar, sizeof(GridBarrier)) != hipSuccess) {
@@ -685,6 +765,23 @@ const char *osqp_error_string(osqp_int code) {
   }
 }
 
+osqp_int osqp_device_info(osqp_int *cu_count, osqp_int *lds_per_block, osqp_int *lds_per_cu,
+                          osqp_int *wall_khz) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OSQP_ERR_NO_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return OSQP_ERR_DEVICE;
+  if (cu_count) *cu_count = prop.multiProcessorCount;
+  if (lds_per_block) *lds_per_block = (osqp_int)prop.sharedMemPerBlock;
+  if (lds_per_cu) *lds_per_cu = (osqp_int)prop.maxSharedMemoryPerMultiProcessor;
+  if (wall_khz) {
+    int w = 0;
+    (void)hipDeviceGetAttribute(&w, hipDeviceAttributeWallClockRate, dev);
+    *wall_khz = w;
+  }
+  return OSQP_OK;
+}
+
 osqp_int osqp_device_count(void) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) return 0;
@@ -782,10 +879,13 @@ osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *
     if (lo > hi) return OSQP_ERR_L_GT_U;
   }
   if (q) std::memcpy(&b->q_raw[d.xo], q, sizeof(double) * d.n);
+  bool eq_changed = false;
   for (int k = 0; k < d.m; ++k) {
     if (l) b->l_raw[d.yo + k] = l[k] <= -kInfBound ? -INFINITY : l[k];
     if (u) b->u_raw[d.yo + k] = u[k] >= kInfBound ? INFINITY : u[k];
-    b->is_eq[d.yo + k] = b->l_raw[d.yo + k] == b->u_raw[d.yo + k];
+    const unsigned char e = b->l_raw[d.yo + k] == b->u_raw[d.yo + k];
+    eq_changed |= (e != b->is_eq[d.yo + k]);
+    b->is_eq[d.yo + k] = e;
   }
   auto push = [&](auto &B) -> int {
     HIPCHK(hipMemcpyAsync((void *)(B.q_raw + d.xo), &b->q_raw[d.xo], sizeof(double) * d.n,
@@ -796,6 +896,12 @@ osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *
       HIPCHK(hipMemcpyAsync((void *)(B.u_raw + d.yo), &b->u_raw[d.yo], sizeof(double) * d.m,
                             hipMemcpyHostToDevice, b->stream));
       HIPCHK(hipMemcpyAsync((void *)(B.is_eq + d.yo), &b->is_eq[d.yo], d.m,
+                            hipMemcpyHostToDevice, b->stream));
+    }
+    if (eq_changed) {
+      // rho_i changes on those rows: the stored dense factor is stale
+      static const double zero = 0.0;
+      HIPCHK(hipMemcpyAsync((void *)&B.st[i].factor_rho, &zero, sizeof(double),
                             hipMemcpyHostToDevice, b->stream));
     }
     return OSQP_OK;
@@ -881,6 +987,35 @@ osqp_int osqp_batch_last_kernel_ms(const osqp_batch *b, double *ms) {
 osqp_int osqp_batch_count(const osqp_batch *b, osqp_int *count) {
   if (!b || !count) return OSQP_ERR_NOT_SETUP;
   *count = b->nq;
+  return OSQP_OK;
+}
+
+osqp_int osqp_batch_get_factor(const osqp_batch *b, osqp_int i, osqp_float *L_out) {
+  if (!b || !L_out) return OSQP_ERR_NOT_SETUP;
+  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
+  const QPDesc &d = b->desc[i];
+  if (!d.dense) return OSQP_ERR_NOT_SETUP;
+  QPState st;
+  const QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
+  if (hipMemcpy(&st, dst + i, sizeof(QPState), hipMemcpyDeviceToHost) != hipSuccess)
+    return OSQP_ERR_DEVICE;
+  if (st.factor_rho == 0.0) return OSQP_ERR_NOT_SETUP;
+  const size_t cnt = (size_t)d.n * d.dld;
+  if (b->fp64) {
+    std::vector<double> tmp(cnt);
+    if (hipMemcpy(tmp.data(), b->bd.dmat + d.dense_off, cnt * sizeof(double),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return OSQP_ERR_DEVICE;
+    for (int r = 0; r < d.n; ++r)
+      for (int c = 0; c < d.n; ++c) L_out[(size_t)r * d.n + c] = c <= r ? tmp[(size_t)r * d.dld + c] : 0.0;
+  } else {
+    std::vector<float> tmp(cnt);
+    if (hipMemcpy(tmp.data(), b->bf.dmat + d.dense_off, cnt * sizeof(float),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return OSQP_ERR_DEVICE;
+    for (int r = 0; r < d.n; ++r)
+      for (int c = 0; c < d.n; ++c) L_out[(size_t)r * d.n + c] = c <= r ? tmp[(size_t)r * d.dld + c] : 0.0;
+  }
   return OSQP_OK;
 }
 

@@ -15,21 +15,70 @@ namespace osqpmi {
 constexpr int kNB = 32;   // Cholesky panel width
 constexpr int kTS = 64;   // trailing-update tile (kTS x kTS outputs)
 
+// LDS of the dense routines.  The factorisation tiles and the diagonal
+// block of a triangular solve are never live at the same time and share
+// storage, which keeps the FP64 instance near 43 KB.
 template <class T>
 struct DenseLDS {
-  T pa[kTS][kNB + 1];
-  T pb[kTS][kNB + 1];
-  T diag[kNB][kNB + 1];
+  union {
+    struct {
+      T pa[kTS][kNB + 1];
+      T pb[kTS][kNB + 1];
+      T diag[kNB][kNB + 1];
+    };
+    T blk[64][65];   // diagonal block of a triangular solve
+  };
+  T ys[64];
   int flag;
 };
 
-// C[I.., J..] -= Pa Pb' for one kTS x kTS tile, depth kd <= kNB, where Pa rows
-// come from the i-range and Pb rows from the j-range (already in LDS).
-// 256 threads: each owns a 4 x 4 block of the tile.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// C[i0.., j0..] += scale * Pa Pb' for one kTS x kTS tile, depth kd <= kNB
+// (Pa holds the i rows, Pb the j rows, both in LDS, zero-padded to kNB).
+// Matrix cores: each of the first four waves owns four 16 x 16 output
+// sub-tiles and runs 16x16x4 MFMAs over the depth.  Operand layout of the
+// 16x16x4 instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[4 (l / 16) + v][l % 16], v = 0..3.
 template <class T>
 __device__ __forceinline__ void tile_gemm_nt(const WGTeam &tm, DenseLDS<T> &s, T *C, int ld,
                                              int i0, int j0, int ni, int nj, int kd,
                                              T scale, bool lower_only) {
+  typedef T vec4 __attribute__((ext_vector_type(4)));
+  const int wv = tm.tid >> 6, lane = tm.tid & 63;
+  if (wv >= 4) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int kpad = (kd + 3) & ~3;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int sub = wv * 4 + q;            // 16 sub-tiles of the 64 x 64 tile
+    const int si = (sub >> 2) * 16, sj = (sub & 3) * 16;
+    vec4 acc = {T(0), T(0), T(0), T(0)};
+    for (int k0 = 0; k0 < kpad; k0 += 4)
+      acc = mfma16x16x4(s.pa[si + li][k0 + lk], s.pb[sj + li][k0 + lk], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = si + 4 * lk + v, j = sj + li;
+      if (i >= ni || j >= nj) continue;
+      if (lower_only && i0 + i < j0 + j) continue;
+      C[(size_t)(i0 + i) * ld + (j0 + j)] += scale * acc[v];
+    }
+  }
+}
+
+// Same tile update on the vector ALUs (kept for reference timing).
+template <class T>
+__device__ __forceinline__ void tile_gemm_nt_valu(const WGTeam &tm, DenseLDS<T> &s, T *C,
+                                                  int ld, int i0, int j0, int ni, int nj, int kd,
+                                                  T scale, bool lower_only) {
   for (int blk = tm.tid; blk < (kTS / 4) * (kTS / 4); blk += tm.nt) {
     const int bi = (blk / (kTS / 4)) * 4, bj = (blk % (kTS / 4)) * 4;
     T acc[4][4];
@@ -63,7 +112,7 @@ __device__ __forceinline__ void tile_gemm_nt(const WGTeam &tm, DenseLDS<T> &s, T
 
 // M (n x n, lower) += scale * B' B with B dense, nr x n, row-major (ldb).
 template <class T>
-__device__ void dense_syrk_tn(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, const T *B,
+__device__ __forceinline__ void dense_syrk_tn(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, const T *B,
                              int ldb, int nr, int n, T scale) {
   for (int i0 = 0; i0 < n; i0 += kTS) {
     const int ni = min(kTS, n - i0);
@@ -87,7 +136,7 @@ __device__ void dense_syrk_tn(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, co
 // In-place Cholesky M = L L' of the lower triangle.  Returns false (to every
 // thread) when a pivot is not positive or not finite.
 template <class T>
-__device__ bool dense_cholesky(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, int n) {
+__device__ __forceinline__ bool dense_cholesky(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, int n) {
   if (tm.tid == 0) s.flag = 0;
   tm.sync();
   for (int kb = 0; kb < n; kb += kNB) {
@@ -119,25 +168,15 @@ __device__ bool dense_cholesky(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, i
       const int r = e / nb, c = e % nb;
       if (c <= r) M[(size_t)(kb + r) * ld + kb + c] = s.diag[r][c];
     }
-    // (b) panel: rows below solve x L_kk' = M_row
+    // (b) panel: each row below solves x L_kk' = M_row in place (its own
+    // nb entries stay in cache; no register array)
     for (int i = kb + nb + tm.tid; i < n; i += tm.nt) {
       T *row = M + (size_t)i * ld + kb;
-      T x[kNB];
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) x[c] = c < nb ? row[c] : T(0);
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) {
-        if (c < nb) {
-          T v = x[c];
-#pragma unroll
-          for (int q = 0; q < kNB; ++q)
-            if (q < c) v -= x[q] * s.diag[c][q];
-          x[c] = v / s.diag[c][c];
-        }
+      for (int c = 0; c < nb; ++c) {
+        T v = row[c];
+        for (int q = 0; q < c; ++q) v -= row[q] * s.diag[c][q];
+        row[c] = v / s.diag[c][c];
       }
-#pragma unroll
-      for (int c = 0; c < kNB; ++c)
-        if (c < nb) row[c] = x[c];
     }
     tm.sync();
     // (c) trailing update of the lower triangle: M22 -= L21 L21'
@@ -163,73 +202,69 @@ __device__ bool dense_cholesky(const WGTeam &tm, DenseLDS<T> &s, T *M, int ld, i
   return ok;
 }
 
-// Solve L y = b in place (b -> y).  L lower, row-major.
+constexpr int kSB = 64;   // triangular-solve block (one wave solves a block)
+
+// Solve L L' x = b in place (b -> x); L lower, row-major (ld).  Each 64-row
+// block is solved by wave 0 in registers (shuffle broadcasts), the rest of
+// the workgroup applies the block to the remaining rows; the forward sweep
+// reads L by row chunks, the backward sweep by coalesced column chunks, so
+// each sweep reads the lower triangle once.
 template <class T>
-__device__ void dense_forward(const WGTeam &tm, DenseLDS<T> &s, const T *L, int ld, int n,
-                              T *b) {
-  for (int kb = 0; kb < n; kb += kNB) {
-    const int nb = min(kNB, n - kb);
-    // diagonal block by one thread (kNB x kNB)
-    if (tm.tid == 0) {
-      for (int c = 0; c < nb; ++c) {
-        T v = b[kb + c];
-        for (int q = 0; q < c; ++q) v -= L[(size_t)(kb + c) * ld + kb + q] * b[kb + q];
-        b[kb + c] = v / L[(size_t)(kb + c) * ld + kb + c];
-      }
+__device__ __forceinline__ void dense_solve_llt(const WGTeam &tm, DenseLDS<T> &s, const T *L, int ld, int n,
+                                T *x) {
+  const int lane = tm.tid & (kWave - 1);
+  const bool w0 = tm.tid < kWave;
+  // forward: L y = b
+  for (int kb = 0; kb < n; kb += kSB) {
+    const int nb = min(kSB, n - kb);
+    for (int e = tm.tid; e < nb * kSB; e += tm.nt) {
+      const int r = e / kSB, c = e % kSB;
+      s.blk[r][c] = (c <= r && c < nb) ? L[(size_t)(kb + r) * ld + kb + c] : T(0);
     }
     tm.sync();
-    // rows below: b_i -= L[i, kb:kb+nb] y_blk
+    if (w0) {
+      T br = lane < nb ? x[kb + lane] : T(0);
+      for (int c = 0; c < nb; ++c) {
+        const T lrc = lane < nb ? s.blk[lane][c] : T(0);
+        const T yc = __shfl(lane == c ? br / lrc : T(0), c, kWave);
+        if (lane == c) br = yc;
+        else if (lane > c) br -= lrc * yc;
+      }
+      if (lane < nb) { x[kb + lane] = br; s.ys[lane] = br; }
+    }
+    tm.sync();
     for (int i = kb + nb + tm.tid; i < n; i += tm.nt) {
-      const T *row = L + (size_t)i * ld + kb;
+      const T *r = L + (size_t)i * ld + kb;
       T acc = T(0);
-      for (int c = 0; c < nb; ++c) acc += row[c] * b[kb + c];
-      b[i] -= acc;
+      for (int c = 0; c < nb; ++c) acc += r[c] * s.ys[c];
+      x[i] -= acc;
     }
     tm.sync();
   }
-}
-
-// Solve L' x = y in place (y -> x).
-template <class T>
-__device__ void dense_backward(const WGTeam &tm, DenseLDS<T> &s, const T *L, int ld, int n,
-                               T *y) {
-  const int nblk = (n + kNB - 1) / kNB;
+  // backward: L' x = y
+  const int nblk = (n + kSB - 1) / kSB;
   for (int bk = nblk - 1; bk >= 0; --bk) {
-    const int kb = bk * kNB, nb = min(kNB, n - kb);
-    // u_c = sum_{i >= kb+nb} L[i, kb+c] x_i, accumulated per thread then
-    // combined through LDS (pa reused as [thread][c] partials in chunks)
-    T part[kNB];
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) part[c] = T(0);
-    for (int i = kb + nb + tm.tid; i < n; i += tm.nt) {
-      const T *row = L + (size_t)i * ld + kb;
-      const T xi = y[i];
-#pragma unroll
-      for (int c = 0; c < kNB; ++c)
-        if (c < nb) part[c] += row[c] * xi;
-    }
-    // reduce over the workgroup: waves shuffle, then LDS across waves
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-      T v = part[c];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-      part[c] = v;
-    }
-    const int wv = tm.tid >> 6, lane = tm.tid & 63;
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) s.pa[wv][c] = part[c];
+    const int kb = bk * kSB, nb = min(kSB, n - kb);
+    for (int e = tm.tid; e < nb * kSB; e += tm.nt) {
+      const int r = e / kSB, c = e % kSB;
+      s.blk[r][c] = (c <= r && c < nb) ? L[(size_t)(kb + r) * ld + kb + c] : T(0);
     }
     tm.sync();
-    if (tm.tid == 0) {
-      const int nw = tm.nt >> 6;
-      for (int c = nb - 1; c >= 0; --c) {
-        T u = T(0);
-        for (int w = 0; w < nw; ++w) u += s.pa[w][c];
-        // within the block: subtract L[kb+r, kb+c] x_{kb+r} for r > c
-        for (int r = c + 1; r < nb; ++r) u += L[(size_t)(kb + r) * ld + kb + c] * y[kb + r];
-        y[kb + c] = (y[kb + c] - u) / L[(size_t)(kb + c) * ld + kb + c];
+    if (w0) {
+      T bs = lane < nb ? x[kb + lane] : T(0);
+      for (int r = nb - 1; r >= 0; --r) {
+        const T lrs = lane < nb ? s.blk[r][lane] : T(0);   // L[r][lane]
+        const T xr = __shfl(lane == r ? bs / lrs : T(0), r, kWave);
+        if (lane == r) bs = xr;
+        else if (lane < r) bs -= lrs * xr;
       }
+      if (lane < nb) { x[kb + lane] = bs; s.ys[lane] = bs; }
+    }
+    tm.sync();
+    for (int j = tm.tid; j < kb; j += tm.nt) {
+      T acc = T(0);
+      for (int r = 0; r < nb; ++r) acc += L[(size_t)(kb + r) * ld + j] * s.ys[r];
+      x[j] -= acc;
     }
     tm.sync();
   }

@@ -17,12 +17,11 @@ __global__ void reset_counters_kernel(int *counter, int ncounters, GridBarrier *
 // Work-queue loop: each workgroup takes the next QP index of `list`
 // (counter slot `slot`) until the list is exhausted.
 template <class F>
-__device__ void wg_queue(int *counter, int nlist, F &&body) {
-  __shared__ int slot_val;
+__device__ __forceinline__ void wg_queue(int *counter, int nlist, int &slot_val, F &&body) {
   for (;;) {
     if (threadIdx.x == 0) slot_val = atomicAdd(counter, 1);
     __syncthreads();
-    const int qi = slot_val;
+    const int qi = __builtin_amdgcn_readfirstlane(slot_val);   // uniform: scalar loads
     __syncthreads();
     if (qi >= nlist) break;
     body(qi);
@@ -34,7 +33,8 @@ __global__ void __launch_bounds__(kMaxBlock) scale_wg_kernel(Batch<T> b, const i
                                                              int nlist, int slot) {
   __shared__ double red[(kMaxBlock / kWave) * kRedSlots];
   WGTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-  wg_queue(b.counter + slot, nlist, [&](int qi) {
+  __shared__ int slot_val;
+  wg_queue(b.counter + slot, nlist, slot_val, [&](int qi) __attribute__((always_inline)) {
     QPView<T> v(b, list[qi]);
     scale_qp<T>(tm, v, b.set);
   });
@@ -52,10 +52,13 @@ template <class T>
 __global__ void __launch_bounds__(kMaxBlock) solve_wg_kernel(Batch<T> b, const int *list,
                                                              int nlist, int slot) {
   __shared__ double red[(kMaxBlock / kWave) * kRedSlots];
+  __shared__ DenseLDS<T> dl;
   WGTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-  wg_queue(b.counter + slot, nlist, [&](int qi) {
+  T *dB = b.dws ? b.dws + (size_t)blockIdx.x * (size_t)b.dws_stride : nullptr;
+  __shared__ int slot_val;
+  wg_queue(b.counter + slot, nlist, slot_val, [&](int qi) __attribute__((always_inline)) {
     QPView<T> v(b, list[qi]);
-    solve_qp<T>(tm, v, b.set);
+    solve_qp<T>(tm, v, b.set, &dl, dB, dB != nullptr);
   });
 }
 
@@ -70,7 +73,8 @@ __global__ void __launch_bounds__(kPolishBlock) polish_wg_kernel(Batch<T> b, con
   __shared__ DenseLDS<double> dl;
   WGTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   double *mine = ws + (size_t)blockIdx.x * (size_t)stride;
-  wg_queue(b.counter + slot, nlist, [&](int qi) {
+  __shared__ int slot_val;
+  wg_queue(b.counter + slot, nlist, slot_val, [&](int qi) __attribute__((always_inline)) {
     const int k = list[qi];
     if (b.st[k].status != 1) return;
     QPView<T> v(b, k);

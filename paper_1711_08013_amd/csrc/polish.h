@@ -27,7 +27,7 @@ struct PolishWS {
 };
 
 template <class T>
-__device__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s, const QPView<T> &v,
+__device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s, const QPView<T> &v,
                           const DevSettings &set, double *ws, int rmax) {
   const int n = v.n, m = v.m;
   const double delta = set.delta, dinv = 1.0 / delta;
@@ -93,8 +93,7 @@ __device__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s, const QPView<T>
     g[j] = -v.q64[j] + a * dinv;
   }
   tm.sync();
-  dense_forward<double>(tm, s, M, n, n, g);
-  dense_backward<double>(tm, s, M, n, n, g);
+  dense_solve_llt<double>(tm, s, M, n, n, g);
   for (int j = tm.tid; j < n; j += tm.nt) tx[j] = g[j];
   tm.sync();
   for (int i = tm.tid; i < m; i += tm.nt) {
@@ -125,8 +124,7 @@ __device__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s, const QPView<T>
       g[j] = rx[j] + a * dinv;
     }
     tm.sync();
-    dense_forward<double>(tm, s, M, n, n, g);
-    dense_backward<double>(tm, s, M, n, n, g);
+    dense_solve_llt<double>(tm, s, M, n, n, g);
     for (int i = tm.tid; i < m; i += tm.nt) {
       double a = 0.0;
       if (act[i] != 0.0)

@@ -16,7 +16,11 @@ struct QPDesc {
   int64_t a_rp, at_rp, p_rp; // row-pointer array offsets (m+1, n+1, n+1 entries)
   int64_t a_nz, at_nz, p_nz; // entry offsets
   int lm, ln;                // lanes per row for passes over A rows / over P+A' rows
-  int dense_off;             // unused by the PCG path
+  int dense;                 // 1: dense factor of P + sigma I + A'RA as PCG preconditioner
+  int dld;                   // leading dimension of that factor
+  int64_t dense_off;         // offset of the factor in the dense arena
+  int64_t mr_off;            // offset of the list of A rows with >= 2 entries
+  int mr_cnt;                // length of that list
   int pad;
 };
 
@@ -28,6 +32,7 @@ struct QPState {
   double prs, drs, pnorm, dnorm;   // scaled residuals / normalisers of the last check
   double solve_ms;      // device wall time of this QP's solve
   double polish_ms;     // device wall time of its polishing step
+  double factor_rho;    // rho-bar the stored dense factor belongs to (0: none)
   int status, iter, pcg_iter, rho_updates, polish_status;
   int init_mode;        // 0 continue, 1 zeros, 2 warm start from xws/yws
   int bad;              // internal failure flag (non-finite PCG scalar etc.)
@@ -67,6 +72,11 @@ struct Batch {
   double *dx, *dy;
   const double *xws, *yws;
   double *xo, *yo, *zo;
+  // dense path: factors, per-workgroup rank-k scratch, multi-entry rows
+  T *dmat;
+  T *dws;
+  long long dws_stride;
+  const int *mrows;
   DevSettings set;
 };
 

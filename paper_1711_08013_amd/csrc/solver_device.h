@@ -8,6 +8,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "dense.h"
 #include "qp_layout.h"
 #include "team.h"
 
@@ -28,8 +31,11 @@ struct QPView {
   const double *xws, *yws;
   double *xo, *yo, *zo;
   QPState *st;
+  T *L;              // dense factor (row-major, lower), when dense
+  int ld, dense, mr_cnt;
+  const int *mrows;
 
-  __device__ QPView(const Batch<T> &b, int k) {
+  __device__ __forceinline__ QPView(const Batch<T> &b, int k) {
     const QPDesc &ds = b.desc[k];
     n = ds.n; m = ds.m; lm = ds.lm; ln = ds.ln;
     arp = b.a_rp + ds.a_rp; aci = b.a_ci + ds.a_nz;
@@ -51,6 +57,9 @@ struct QPView {
     xws = b.xws + ds.xo; yws = b.yws + ds.yo;
     xo = b.xo + ds.xo; yo = b.yo + ds.yo; zo = b.zo + ds.yo;
     st = b.st + k;
+    dense = ds.dense; ld = ds.dld; mr_cnt = ds.mr_cnt;
+    L = ds.dense ? b.dmat + ds.dense_off : nullptr;
+    mrows = b.mrows + ds.mr_off;
   }
 };
 
@@ -58,7 +67,7 @@ struct QPView {
 struct Rows {
   int g, lane, ng, L;
   template <class Team>
-  __device__ Rows(const Team &tm, int L_) : L(L_) {
+  __device__ __forceinline__ Rows(const Team &tm, int L_) : L(L_) {
     g = tm.tid / L; lane = tm.tid & (L - 1); ng = tm.nt / L;
   }
 };
@@ -89,7 +98,7 @@ __device__ __forceinline__ double scale_a(double raw, double Ei, double Dj) {
 // resident unscaled data; then writes the scaled data in T and in double.
 // ------------------------------------------------------------------------
 template <class T, class Team>
-__device__ void scale_qp(const Team &tm, const QPView<T> &v, const DevSettings &set) {
+__device__ __forceinline__ void scale_qp(const Team &tm, const QPView<T> &v, const DevSettings &set) {
   const int n = v.n, m = v.m;
   for (int j = tm.tid; j < n; j += tm.nt) v.D[j] = 1.0;
   for (int i = tm.tid; i < m; i += tm.nt) v.E[i] = 1.0;
@@ -181,7 +190,7 @@ __device__ void scale_qp(const Team &tm, const QPView<T> &v, const DevSettings &
 
 // Rescale new vectors (q, l, u) with the stored D, E, c (Section 6).
 template <class T, class Team>
-__device__ void rescale_vectors(const Team &tm, const QPView<T> &v) {
+__device__ __forceinline__ void rescale_vectors(const Team &tm, const QPView<T> &v) {
   const double c = v.st->c;
   for (int j = tm.tid; j < v.n; j += tm.nt) {
     const double qq = c * v.D[j] * v.qraw[j];
@@ -197,7 +206,7 @@ __device__ void rescale_vectors(const Team &tm, const QPView<T> &v) {
 // rho_i = rho-bar (l_i != u_i) or 1e3 rho-bar (l_i == u_i), Section 5.2;
 // Jacobi preconditioner of P + sigma I + A' R A: diag(P) + sigma + sum_i rho_i A_ij^2.
 template <class T, class Team>
-__device__ void set_rho_and_precond(const Team &tm, const QPView<T> &v, double rho_bar,
+__device__ __forceinline__ void set_rho_and_precond(const Team &tm, const QPView<T> &v, double rho_bar,
                                     double sigma) {
   for (int i = tm.tid; i < v.m; i += tm.nt) {
     const double r = v.iseq[i] ? 1e3 * rho_bar : rho_bar;
@@ -219,11 +228,55 @@ __device__ void set_rho_and_precond(const Team &tm, const QPView<T> &v, double r
 }
 
 // ------------------------------------------------------------------------
+// Dense path: form Kbar = P + sigma I + A' R A (rows of A with one entry
+// add to the diagonal, the others through the rank-k update B'B with
+// B = R^1/2 A restricted to them) and factor it, Kbar = L L'.
+// ------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ bool form_and_factor(const WGTeam &tm, const QPView<T> &v, DenseLDS<T> &s, T *B,
+                                double sigma) {
+  const int n = v.n, ld = v.ld, R = v.mr_cnt;
+  for (size_t e = tm.tid; e < (size_t)n * ld; e += tm.nt) v.L[e] = T(0);
+  for (size_t e = tm.tid; e < (size_t)R * n; e += tm.nt) B[e] = T(0);
+  tm.sync();
+  for (int j = tm.tid; j < n; j += tm.nt) {
+    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) {
+      const int c = v.pci[k];
+      if (c <= j) v.L[(size_t)j * ld + c] = v.pv[k];
+    }
+    T dsum = T(sigma);
+    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
+      const int i = v.atci[k];
+      if (v.arp[i + 1] - v.arp[i] == 1) dsum += v.rho[i] * v.atv[k] * v.atv[k];
+    }
+    v.L[(size_t)j * ld + j] += dsum;
+  }
+  for (int r = tm.tid; r < R; r += tm.nt) {
+    const int i = v.mrows[r];
+    const T sr = T(sqrt(double(v.rho[i])));
+    for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) B[(size_t)r * n + v.aci[k]] = sr * v.av[k];
+  }
+  tm.sync();
+  dense_syrk_tn<T>(tm, s, v.L, ld, B, n, R, n, T(1));
+  return dense_cholesky<T>(tm, s, v.L, ld, n);
+}
+
+// d = (L L')^-1 r
+template <class T>
+__device__ __forceinline__ void precondition_dense(const WGTeam &tm, const QPView<T> &v, DenseLDS<T> &s) {
+  tm.sync();
+  for (int j = tm.tid; j < v.n; j += tm.nt) v.d[j] = v.r[j];
+  tm.sync();
+  dense_solve_llt<T>(tm, s, v.L, v.ld, v.n, v.d);
+}
+
+// ------------------------------------------------------------------------
 // One full solve of one QP (Algorithm 1 with the reduced-system PCG of
 // Section 3.1), then the FP64 checks, statuses and unscaled outputs.
 // ------------------------------------------------------------------------
 template <class T, class Team>
-__device__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &set) {
+__device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &set,
+                         DenseLDS<T> *dl = nullptr, T *dB = nullptr, bool dense_ok = false) {
   const int n = v.n, m = v.m;
   const T sigma = T(set.sigma), alpha = T(set.alpha), one_m_alpha = T(1.0 - set.alpha);
   const double c = v.st->c, cinv = 1.0 / c;
@@ -232,6 +285,18 @@ __device__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &
   const unsigned long long t_start = wall_clock64();
 
   set_rho_and_precond(tm, v, rho_bar, set.sigma);
+  // dense preconditioner: reuse the stored factor while rho-bar is unchanged
+  bool use_dense = false;
+  if constexpr (std::is_same<Team, WGTeam>::value) {
+    if (v.dense && dense_ok) {
+      use_dense = true;
+      if (v.st->factor_rho != rho_bar) {
+        use_dense = form_and_factor<T>(tm, v, *dl, dB, set.sigma);
+        if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
+        tm.sync();
+      }
+    }
+  }
 
   // initial iterate: continue, zeros, or the warm start of Section 6
   const int mode = v.st->init_mode;
@@ -282,10 +347,23 @@ __device__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &
       a = group_sum(a, rn.L);
       if (rn.lane == 0) {
         const T rj = sigma * (v.x[j] - v.xt[j]) - v.q[j] + a;
-        const T dj = v.minv[j] * rj;
-        v.r[j] = rj; v.d[j] = dj; v.p[j] = dj;
-        red[0] += double(rj * dj);
+        v.r[j] = rj;
         red[1] = fmax(red[1], fabs(double(rj)));
+        if (!use_dense) {
+          const T dj = v.minv[j] * rj;
+          v.d[j] = dj; v.p[j] = dj;
+          red[0] += double(rj * dj);
+        }
+      }
+    }
+    if constexpr (std::is_same<Team, WGTeam>::value) {
+      if (use_dense) {
+        precondition_dense(tm, v, *dl);
+        for (int j = tm.tid; j < n; j += tm.nt) {
+          const T dj = v.d[j];
+          v.p[j] = dj;
+          red[0] += double(v.r[j] * dj);
+        }
       }
     }
     tm.template reduce<1, 1>(red);
@@ -326,10 +404,19 @@ __device__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &
       for (int j = tm.tid; j < n; j += tm.nt) {
         v.xt[j] += a_step * v.p[j];
         const T rj = v.r[j] - a_step * v.w[j];
-        const T dj = v.minv[j] * rj;
-        v.r[j] = rj; v.d[j] = dj;
-        red[0] += double(rj * dj);
+        v.r[j] = rj;
         red[1] = fmax(red[1], fabs(double(rj)));
+        if (!use_dense) {
+          const T dj = v.minv[j] * rj;
+          v.d[j] = dj;
+          red[0] += double(rj * dj);
+        }
+      }
+      if constexpr (std::is_same<Team, WGTeam>::value) {
+        if (use_dense) {
+          precondition_dense(tm, v, *dl);
+          for (int j = tm.tid; j < n; j += tm.nt) red[0] += double(v.r[j] * v.d[j]);
+        }
       }
       tm.template reduce<1, 1>(red);
       const T beta = T(red[0] / rz);
@@ -481,6 +568,12 @@ __device__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &
         rho_bar = rnew;
         ++rho_updates;
         set_rho_and_precond(tm, v, rho_bar, set.sigma);
+        if constexpr (std::is_same<Team, WGTeam>::value) {
+          if (v.dense && dense_ok) {
+            use_dense = form_and_factor<T>(tm, v, *dl, dB, set.sigma);
+            if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
+          }
+        }
         for (int i = tm.tid; i < m; i += tm.nt)
           v.s[i] = v.rho[i] * (v.z[i] - v.zt[i]) - v.y[i];
         tm.sync();

@@ -47,12 +47,12 @@ struct WGTeam {
   int tid, nt;
   double *red;   // LDS, (nt/64) * kRedSlots doubles
 
-  __device__ void sync() const { __syncthreads(); }
+  __device__ __forceinline__ void sync() const { __syncthreads(); }
 
   // In-place reduction of NS sums followed by NM maxima (NS + NM <= kRedSlots);
   // every thread receives the team-wide results.
   template <int NS, int NM>
-  __device__ void reduce(double *v) const {
+  __device__ __forceinline__ void reduce(double *v) const {
     static_assert(NS + NM <= kRedSlots, "too many values");
     const int lane = tid & (kWave - 1), wv = tid >> 6, nw = nt >> 6;
 #pragma unroll
@@ -93,7 +93,7 @@ struct GridTeam {
   GridBarrier *bar;
   mutable int phase;      // alternates the partials buffer between reductions
 
-  __device__ void sync() const {
+  __device__ __forceinline__ void sync() const {
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
@@ -123,7 +123,7 @@ struct GridTeam {
   }
 
   template <int NS, int NM>
-  __device__ void reduce(double *v) const {
+  __device__ __forceinline__ void reduce(double *v) const {
     static_assert(NS + NM <= kRedSlots, "too many values");
     const int lt = threadIdx.x;
     const int lane = lt & (kWave - 1), wv = lt >> 6, nw = blockDim.x >> 6;

@@ -224,3 +224,42 @@ def test_portfolio_polished_parity(pm):
               f"err={rows[-1]['obj_err']:.2e}", flush=True)
     errs = gc.summarize(rows, "portfolio x12 polished")
     assert max(errs) <= gc.OBJ_TOL
+
+
+@pytest.mark.parametrize("linsys", ["dense", "pcg"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_linear_system_paths_agree(pm, linsys, precision):
+    """Both reduced-system solvers -- PCG preconditioned by the dense
+    Cholesky factor of P + sigma I + A'RA, and Jacobi-preconditioned PCG --
+    reach the oracle's status and objective on MPC and portfolio instances."""
+    qps = [qpgen.config_instance(3, i) for i in range(8)] + \
+          [qpgen.config_instance(4, i, n_range=(100, 400)) for i in range(4)]
+    print(f"linsys={linsys} {precision}", flush=True)
+    res = _solve_batch(pm, qps, precision=precision, linsys=linsys)
+    rows = [gc.compare(q, *r, oracle.solve(q)) for q, r in zip(qps, res)]
+    gc.summarize(rows, f"linsys={linsys} {precision}")
+    its = [r[2]["pcg_iter"] / max(1, r[2]["iter"]) for r in res]
+    print(f"  mean pcg per admm step {np.mean(its):.2f}", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_dense_factor_is_cholesky_of_reduced_matrix(pm, precision):
+    """The MFMA-formed, MFMA-factored dense matrix: L L' equals
+    Pbar + sigma I + Abar' R Abar recomputed in numpy from the scaled data
+    (scaling from the oracle's independent Ruiz, same passes and readings)."""
+    qps = [qpgen.config_instance(1, 0), qpgen.config_instance(3, 1),
+           qpgen.config_instance(4, 2, n_range=(100, 300))]
+    b = pm.Batch(qps, precision=precision, linsys="dense", max_iter=1, adaptive_rho=0)
+    b.solve()
+    for i, qp in enumerate(qps):
+        L = b.factor(i)
+        D, E, c = oracle.ruiz(qp, 10)
+        Pb = c * (D[:, None] * qp.full_P().toarray() * D[None, :])
+        Ab = E[:, None] * qp.A.toarray() * D[None, :]
+        rho = np.where(qp.l == qp.u, 1e3 * 0.1, 0.1)
+        K = Pb + 1e-6 * np.eye(qp.n) + Ab.T @ (rho[:, None] * Ab)
+        err = np.max(np.abs(L @ L.T - K)) / np.max(np.abs(K))
+        tol = 2e-5 if precision == "fp32" else 1e-12
+        print(f"  {qp.name} {precision}: rel err of L L' {err:.2e}", flush=True)
+        assert err <= tol, err
+    b.close()
