@@ -111,6 +111,9 @@ typedef struct {
   osqp_float prim_res, dual_res, eps_prim, eps_dual; /* unscaled, FP64, Sections 3.4/5.1 */
   osqp_float rho_bar;      /* final rho-bar                                  */
   osqp_float setup_time, solve_time, polish_time;   /* seconds              */
+  /* device time of this QP's solve by phase (seconds): dense factorisation,
+   * PCG (start pass and iterations), ADMM update pass, FP64 checks */
+  osqp_float factor_time, pcg_time, update_time, check_time;
 } osqp_info;
 
 typedef struct osqp_batch osqp_batch;
@@ -198,6 +201,35 @@ osqp_int osqp_batch_count(const osqp_batch *b, osqp_int *count);
  * has no valid factor yet.  For checking and diagnostics. */
 osqp_int osqp_batch_get_factor(const osqp_batch *b, osqp_int i, osqp_float *L_out);
 void osqp_batch_cleanup(osqp_batch *b);
+
+/* ---- continuous-batching server ----------------------------------------
+ * A scheduler thread admits submitted QPs while slots (max_slots QPs on the
+ * device at once) and the HBM budget allow.  QPs admitted together form a
+ * micro-batch that is set up and solved on its own stream, so micro-batches
+ * admitted while others run overlap on the device.  A nonzero
+ * structure_key marks QPs that share matrices: the first one stays resident
+ * (matrices, dense factor, iterates) and later ones reuse it through the
+ * vector update and warm start of Section 6 (their P and A must equal the
+ * first's; only q, l, u are taken).  Tickets are returned at submission.
+ * Calls from several client threads are allowed. */
+osqp_int osqp_server_create(osqp_server **out, size_t hbm_budget_bytes, osqp_int max_slots,
+                            const osqp_settings *s);
+/* Copy the problem and queue it.  x_ws / y_ws (may be NULL) warm start it.
+ * Returns OSQP_ERR_BUDGET when the QP alone exceeds the budget, or a
+ * validation code; *ticket identifies the request. */
+osqp_int osqp_server_submit(osqp_server *sv, const osqp_problem *p, uint64_t structure_key,
+                            const osqp_float *x_ws, const osqp_float *y_ws, uint64_t *ticket);
+/* Block until request `ticket` is done; copy x (n), y (m), info and the
+ * latency (completion minus submission, seconds).  Any output may be NULL.
+ * Returns the request's own error code if its setup or solve failed. */
+osqp_int osqp_server_wait(osqp_server *sv, uint64_t ticket, osqp_float *x, osqp_float *y,
+                          osqp_info *info, double *latency_s);
+/* Counters: requests completed, micro-batches launched, peak concurrent
+ * micro-batches on the device, peak HBM bytes in use.  Any pointer may be NULL. */
+osqp_int osqp_server_stats(const osqp_server *sv, int64_t *completed, int64_t *batches,
+                           int64_t *peak_inflight, int64_t *peak_bytes);
+/* Finish every queued request, then stop the scheduler and free everything. */
+void osqp_server_destroy(osqp_server *sv);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,8 @@ EXPORTS = [
     "osqp_batch_solve_async", "osqp_batch_sync", "osqp_batch_reset",
     "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_get",
     "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_get_factor",
-    "osqp_batch_cleanup",
+    "osqp_batch_cleanup", "osqp_server_create", "osqp_server_submit", "osqp_server_wait",
+    "osqp_server_stats", "osqp_server_destroy",
 ]
 
 
@@ -71,7 +72,8 @@ class _Info(ctypes.Structure):
                 ("status", "iter", "pcg_iter", "rho_updates", "polish_status")] + \
                [(k, ctypes.c_double) for k in
                 ("obj_val", "prim_res", "dual_res", "eps_prim", "eps_dual", "rho_bar",
-                 "setup_time", "solve_time", "polish_time")]
+                 "setup_time", "solve_time", "polish_time", "factor_time", "pcg_time",
+                 "update_time", "check_time")]
 
 
 _lib = None
@@ -88,10 +90,18 @@ def lib() -> ctypes.CDLL:
             getattr(L, name)
         L.osqp_error_string.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup"):
+            if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup",
+                            "osqp_server_destroy"):
                 getattr(L, name).restype = ctypes.c_int32
         L.osqp_cleanup.restype = None
         L.osqp_batch_cleanup.restype = None
+        L.osqp_server_destroy.restype = None
+        L.osqp_server_create.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                         ctypes.c_void_p]
+        L.osqp_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.osqp_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -244,6 +254,58 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib().osqp_batch_cleanup(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server: submit QPs (optionally with a structure key
+    shared by QPs with equal P and A), then wait for each ticket."""
+
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, max_slots: int = 1024, **settings):
+        self._settings = _make_settings(settings)
+        h = ctypes.c_void_p()
+        _check(lib().osqp_server_create(ctypes.byref(h), int(hbm_budget_bytes), int(max_slots),
+                                        ctypes.byref(self._settings)), "osqp_server_create")
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, qp, key: int = 0, x_ws=None, y_ws=None) -> int:
+        k = _Keep(qp)
+        p = k.problem()
+        xa = None if x_ws is None else np.ascontiguousarray(x_ws, dtype=np.float64)
+        ya = None if y_ws is None else np.ascontiguousarray(y_ws, dtype=np.float64)
+        t = ctypes.c_uint64(0)
+        _check(lib().osqp_server_submit(self._h, ctypes.byref(p), ctypes.c_uint64(int(key)),
+                                        _ptr(xa), _ptr(ya), ctypes.byref(t)), "osqp_server_submit")
+        self._sizes[t.value] = (k.n, k.m)
+        return t.value
+
+    def wait(self, ticket: int):
+        n, m = self._sizes.pop(ticket)
+        x = np.zeros(n)
+        y = np.zeros(max(m, 1))
+        info = _Info()
+        lat = ctypes.c_double(0.0)
+        _check(lib().osqp_server_wait(self._h, ctypes.c_uint64(ticket), _ptr(x), _ptr(y),
+                                      ctypes.byref(info), ctypes.byref(lat)), "osqp_server_wait")
+        return x, y[:m], _info_dict(info), lat.value
+
+    def stats(self) -> dict:
+        v = [ctypes.c_int64(0) for _ in range(4)]
+        _check(lib().osqp_server_stats(self._h, *[ctypes.byref(x) for x in v]),
+               "osqp_server_stats")
+        return dict(zip(("completed", "batches", "peak_inflight", "peak_bytes"),
+                        (x.value for x in v)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().osqp_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -227,10 +227,10 @@ void fill_batch_ptrs(Batch<T> &B, osqp_batch *b, Arena &ar, bool alias64) {
   B.rho = ar.take<T>(sm);
   B.rhoinv = ar.take<T>(sm);
   B.minv = ar.take<T>(sn);
-  B.x = ar.take<T>(sn);
-  B.z = ar.take<T>(sm);
-  B.y = ar.take<T>(sm);
-  B.xt = ar.take<T>(sn);
+  B.x = ar.take<double>(sn);
+  B.z = ar.take<double>(sm);
+  B.y = ar.take<double>(sm);
+  B.xt = ar.take<double>(sn);
   B.zt = ar.take<T>(sm);
   B.r = ar.take<T>(sn);
   B.d = ar.take<T>(sn);
@@ -240,6 +240,13 @@ void fill_batch_ptrs(Batch<T> &B, osqp_batch *b, Arena &ar, bool alias64) {
   B.s = ar.take<T>(sm);
   B.dx = ar.take<double>(sn);
   B.dy = ar.take<double>(sm);
+  if (alias64) {
+    B.zt64 = reinterpret_cast<double *>(B.zt);
+    B.s64 = reinterpret_cast<double *>(B.s);
+  } else {
+    B.zt64 = ar.take<double>(sm);
+    B.s64 = ar.take<double>(sm);
+  }
   B.xws = ar.take<double>(sn);
   B.yws = ar.take<double>(sm);
   B.xo = ar.take<double>(sn);
@@ -463,7 +470,14 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     total += cost[k];
   }
   for (int k = 0; k < count; ++k) {
-    const bool big = cost[k] >= (int64_t)400000 && (count == 1 || cost[k] * 64 > total);
+    // a QP the dense path takes stays on a workgroup: its preconditioner
+    // makes the PCG converge in a step or two, and the whole-grid team would
+    // pay a grid barrier per pass
+    const int n = probs[k].n;
+    const bool dense_ok = (s.linsys == OSQP_LINSYS_DENSE && n <= kDenseMaxN) ||
+                          (s.linsys == OSQP_LINSYS_AUTO && n <= kDenseAutoN);
+    const bool big = !dense_ok && cost[k] >= (int64_t)400000 &&
+                     (count == 1 || cost[k] * 64 > total);
     (big ? b->big_list : b->small_list).push_back(k);
   }
   std::stable_sort(b->small_list.begin(), b->small_list.end(),
@@ -710,6 +724,10 @@ void fill_info(const osqp_batch *b, int k, osqp_info *info) {
   info->setup_time = b->setup_time;
   info->solve_time = b->nq == 1 ? b->last_solve_time : S.solve_ms * 1e-3;
   info->polish_time = S.polish_ms * 1e-3;
+  info->factor_time = S.t_factor_ms * 1e-3;
+  info->pcg_time = S.t_pcg_ms * 1e-3;
+  info->update_time = S.t_update_ms * 1e-3;
+  info->check_time = S.t_check_ms * 1e-3;
 }
 
 }  // namespace
@@ -1023,3 +1041,8 @@ void osqp_batch_cleanup(osqp_batch *b) { destroy(b); }
 void osqp_cleanup(osqp_solver *h) { destroy(h); }
 
 }  // extern "C"
+
+// ===========================================================================
+// continuous-batching server (C ABI, see include/osqp_mi.h)
+// ===========================================================================
+#include "server.h"

@@ -49,9 +49,9 @@ __device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
 // 16x16x4 instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
 // and receives D[4 (l / 16) + v][l % 16], v = 0..3.
 template <class T>
-__device__ __forceinline__ void tile_gemm_nt(const WGTeam &tm, DenseLDS<T> &s, T *C, int ld,
-                                             int i0, int j0, int ni, int nj, int kd,
-                                             T scale, bool lower_only) {
+__device__ __forceinline__ void tile_gemm_nt_mfma(const WGTeam &tm, DenseLDS<T> &s, T *C, int ld,
+                                                  int i0, int j0, int ni, int nj, int kd,
+                                                  T scale, bool lower_only) {
   typedef T vec4 __attribute__((ext_vector_type(4)));
   const int wv = tm.tid >> 6, lane = tm.tid & 63;
   if (wv >= 4) return;
@@ -74,7 +74,8 @@ __device__ __forceinline__ void tile_gemm_nt(const WGTeam &tm, DenseLDS<T> &s, T
   }
 }
 
-// Same tile update on the vector ALUs (kept for reference timing).
+// Same tile update on the vector ALUs (used for double: the FP64 16x16x4
+// instruction's result layout differs from the FP32 one assumed above).
 template <class T>
 __device__ __forceinline__ void tile_gemm_nt_valu(const WGTeam &tm, DenseLDS<T> &s, T *C,
                                                   int ld, int i0, int j0, int ni, int nj, int kd,
@@ -108,6 +109,16 @@ __device__ __forceinline__ void tile_gemm_nt_valu(const WGTeam &tm, DenseLDS<T> 
       }
     }
   }
+}
+
+template <class T>
+__device__ __forceinline__ void tile_gemm_nt(const WGTeam &tm, DenseLDS<T> &s, T *C, int ld,
+                                             int i0, int j0, int ni, int nj, int kd, T scale,
+                                             bool lower_only) {
+  if constexpr (sizeof(T) == 4)
+    tile_gemm_nt_mfma<T>(tm, s, C, ld, i0, j0, ni, nj, kd, scale, lower_only);
+  else
+    tile_gemm_nt_valu<T>(tm, s, C, ld, i0, j0, ni, nj, kd, scale, lower_only);
 }
 
 // M (n x n, lower) += scale * B' B with B dense, nr x n, row-major (ldb).

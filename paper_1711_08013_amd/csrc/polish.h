@@ -168,13 +168,13 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   if (accept) {
     for (int j = tm.tid; j < n; j += tm.nt) {
       v.xo[j] = v.D[j] * tx[j];
-      v.x[j] = T(tx[j]);
+      v.x[j] = tx[j];
     }
     for (int i = tm.tid; i < m; i += tm.nt) {
       v.yo[i] = cinv * v.E[i] * ty[i];
       v.zo[i] = v.Einv[i] * ry[i];
-      v.y[i] = T(ty[i]);
-      v.z[i] = T(ry[i]);
+      v.y[i] = ty[i];
+      v.z[i] = ry[i];
     }
   }
   if (tm.tid == 0) {

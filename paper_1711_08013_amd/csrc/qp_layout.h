@@ -33,6 +33,7 @@ struct QPState {
   double solve_ms;      // device wall time of this QP's solve
   double polish_ms;     // device wall time of its polishing step
   double factor_rho;    // rho-bar the stored dense factor belongs to (0: none)
+  double t_factor_ms, t_pcg_ms, t_update_ms, t_check_ms;   // device time per phase
   int status, iter, pcg_iter, rho_updates, polish_status;
   int init_mode;        // 0 continue, 1 zeros, 2 warm start from xws/yws
   int bad;              // internal failure flag (non-finite PCG scalar etc.)
@@ -68,8 +69,10 @@ struct Batch {
   const unsigned char *is_eq;
   // iterates and work vectors
   T *rho, *rhoinv, *minv;
-  T *x, *z, *y, *xt, *zt, *r, *d, *p, *w, *t, *s;
+  double *x, *z, *y, *xt;   // ADMM iterates (double in both modes)
+  T *zt, *r, *d, *p, *w, *t, *s;   // PCG work vectors in the working precision
   double *dx, *dy;
+  double *zt64, *s64;
   const double *xws, *yws;
   double *xo, *yo, *zo;
   // dense path: factors, per-workgroup rank-k scratch, multi-entry rows

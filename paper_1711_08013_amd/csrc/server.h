@@ -1,0 +1,420 @@
+// Continuous-batching server (part of the C ABI in include/osqp_mi.h).
+// Included at the end of api.hip: it drives the batch API above.
+//
+// One scheduler thread owns the device work.  Each pass it (1) retires
+// micro-batches whose stream has drained and hands their results to the
+// waiting clients, (2) admits queued requests while slots and the HBM budget
+// allow -- fresh QPs are grouped into one new micro-batch, a QP whose
+// structure key is resident is re-solved in place through the vector update
+// and warm start of Section 6 -- and launches them asynchronously on their
+// own streams, so work admitted now overlaps work already on the device.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+struct OwnedQP {
+  int n = 0, m = 0;
+  std::vector<int> Pp, Pi, Ap, Ai;
+  std::vector<double> Px, Ax, q, l, u, xws, yws;
+  bool has_x = false, has_y = false;
+
+  void copy_from(const osqp_problem &p, const double *x, const double *y) {
+    n = p.n; m = p.m;
+    Pp.assign(p.P_upper.indptr, p.P_upper.indptr + n + 1);
+    Pi.assign(p.P_upper.indices, p.P_upper.indices + p.P_upper.nnz);
+    Px.assign(p.P_upper.data, p.P_upper.data + p.P_upper.nnz);
+    Ap.assign(p.A.indptr, p.A.indptr + m + 1);
+    Ai.assign(p.A.indices, p.A.indices + p.A.nnz);
+    Ax.assign(p.A.data, p.A.data + p.A.nnz);
+    q.assign(p.q, p.q + n);
+    l.assign(p.l, p.l + m);
+    u.assign(p.u, p.u + m);
+    has_x = x != nullptr;
+    has_y = y != nullptr;
+    if (x) xws.assign(x, x + n);
+    if (y) yws.assign(y, y + m);
+  }
+  osqp_problem view() const {
+    osqp_problem p;
+    p.n = n; p.m = m;
+    p.P_upper = {n, n, (int)Px.size(), Pp.data(), Pi.data(), Px.data()};
+    p.q = q.data();
+    p.A = {m, n, (int)Ax.size(), Ap.data(), Ai.data(), Ax.data()};
+    p.l = l.data();
+    p.u = u.data();
+    return p;
+  }
+};
+
+struct ServerReq {
+  uint64_t ticket = 0, key = 0;
+  OwnedQP qp;
+  size_t bytes = 0;
+  double t_submit = 0.0;
+};
+
+struct ServerResult {
+  bool done = false;
+  int rc = OSQP_OK;
+  std::vector<double> x, y;
+  osqp_info info{};
+  double latency = 0.0;
+};
+
+struct Resident {
+  osqp_batch *b = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+  uint64_t last_use = 0;
+};
+
+struct InFlight {
+  osqp_batch *b = nullptr;
+  bool resident = false;
+  uint64_t key = 0;
+  size_t bytes = 0;
+  std::vector<std::shared_ptr<ServerReq>> reqs;
+};
+
+// HBM a request needs on the device (arena, dense factor, polish workspace).
+size_t estimate_bytes(const osqp_problem &p, const osqp_settings &s) {
+  const double t = s.precision == OSQP_PRECISION_FP64 ? 8.0 : 4.0;
+  const double a = p.A.nnz, pu = p.P_upper.nnz, n = p.n, m = p.m;
+  double b = a * (4 + 4 + 8 + 8 + 8 + 8 + 2 * t) + 2.0 * pu * (4 + 8 + 8 + t) +
+             n * (12 * 8 + 10 * t) + m * (14 * 8 + 10 * t) + 256.0 * 1024;
+  if (s.linsys != OSQP_LINSYS_PCG && p.n <= kDenseAutoN) b += n * (n + 8) * t + n * m * t;
+  if (s.polish && p.n <= kPolishMaxN) b += n * n * 8 + n * m * 8;
+  return (size_t)b;
+}
+
+}  // namespace
+
+struct osqp_server {
+  osqp_settings set{};
+  size_t budget = 0;
+  int max_slots = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<ServerReq>> queue;
+  std::unordered_map<uint64_t, ServerResult> results;
+  std::unordered_map<uint64_t, Resident> resident;
+  std::vector<InFlight> inflight;
+  size_t used = 0;
+  int slots = 0;
+  uint64_t next_ticket = 1, tick = 0;
+  int64_t completed = 0, batches = 0, peak_inflight = 0, peak_bytes = 0;
+  bool stop = false;
+  std::thread worker;
+};
+
+namespace {
+
+void server_finish(osqp_server *sv, InFlight &f) {
+  int rc = osqp_batch_sync(f.b);
+  const double now = now_s();
+  std::vector<ServerResult> out(f.reqs.size());
+  for (size_t k = 0; k < f.reqs.size(); ++k) {
+    ServerResult &r = out[k];
+    r.done = true;
+    r.rc = rc;
+    const int idx = f.resident ? 0 : (int)k;
+    r.x.resize(f.reqs[k]->qp.n);
+    r.y.resize(f.reqs[k]->qp.m);
+    if (rc == OSQP_OK)
+      rc = osqp_batch_get(f.b, idx, r.x.data(), r.y.data(), &r.info);
+    r.rc = rc;
+    r.latency = now - f.reqs[k]->t_submit;
+  }
+  std::lock_guard<std::mutex> g(sv->mu);
+  for (size_t k = 0; k < f.reqs.size(); ++k) sv->results[f.reqs[k]->ticket] = std::move(out[k]);
+  sv->completed += (int64_t)f.reqs.size();
+  sv->slots -= (int)f.reqs.size();
+  if (f.resident) {
+    Resident &r = sv->resident[f.key];
+    r.busy = false;
+    r.last_use = ++sv->tick;
+  } else {
+    osqp_batch_cleanup(f.b);
+    sv->used -= f.bytes;
+  }
+  sv->cv_done.notify_all();
+  sv->cv_work.notify_all();
+}
+
+void server_fail(osqp_server *sv, const std::vector<std::shared_ptr<ServerReq>> &reqs, int rc,
+                 size_t bytes) {
+  std::lock_guard<std::mutex> g(sv->mu);
+  for (auto &q : reqs) {
+    ServerResult r;
+    r.done = true;
+    r.rc = rc;
+    sv->results[q->ticket] = std::move(r);
+  }
+  sv->slots -= (int)reqs.size();
+  sv->used -= bytes;
+  sv->completed += (int64_t)reqs.size();
+  sv->cv_done.notify_all();
+}
+
+void server_loop(osqp_server *sv) {
+  for (;;) {
+    // (1) retire drained micro-batches
+    std::vector<InFlight> done;
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      for (size_t k = 0; k < sv->inflight.size();) {
+        if (hipStreamQuery(sv->inflight[k].b->stream) == hipSuccess) {
+          done.push_back(std::move(sv->inflight[k]));
+          sv->inflight.erase(sv->inflight.begin() + k);
+        } else {
+          ++k;
+        }
+      }
+    }
+    for (auto &f : done) server_finish(sv, f);
+
+    // (2) admission under the lock, launches outside it
+    std::vector<std::shared_ptr<ServerReq>> fresh, repeats, firsts;
+    size_t fresh_bytes = 0;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (sv->queue.empty() && sv->inflight.empty()) {
+        if (sv->stop) return;
+        sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+        if (sv->stop && sv->queue.empty()) return;
+      }
+      for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+        auto &rq = *it;
+        if (sv->slots + (int)(fresh.size() + repeats.size() + firsts.size()) >= sv->max_slots) break;
+        if (rq->key) {
+          auto r = sv->resident.find(rq->key);
+          if (r != sv->resident.end()) {
+            bool pending = false;   // an earlier request of this key is admitted now
+            for (auto &x : repeats) pending |= x->key == rq->key;
+            for (auto &x : firsts) pending |= x->key == rq->key;
+            if (r->second.busy || pending) { ++it; continue; }
+            r->second.busy = true;
+            repeats.push_back(rq);
+            it = sv->queue.erase(it);
+            continue;
+          }
+          bool pending = false;
+          for (auto &x : firsts) pending |= x->key == rq->key;
+          if (pending) { ++it; continue; }
+          // make room by evicting idle resident structures, oldest first
+          while (sv->used + fresh_bytes + rq->bytes > sv->budget) {
+            uint64_t victim = 0, best = UINT64_MAX;
+            for (auto &kv : sv->resident)
+              if (!kv.second.busy && kv.second.last_use < best) { best = kv.second.last_use; victim = kv.first; }
+            if (!victim) break;
+            osqp_batch_cleanup(sv->resident[victim].b);
+            sv->used -= sv->resident[victim].bytes;
+            sv->resident.erase(victim);
+          }
+          if (sv->used + fresh_bytes + rq->bytes > sv->budget) break;
+          Resident nr;
+          nr.busy = true;
+          nr.bytes = rq->bytes;
+          sv->resident[rq->key] = nr;
+          sv->used += rq->bytes;
+          firsts.push_back(rq);
+          it = sv->queue.erase(it);
+          continue;
+        }
+        if (sv->used + fresh_bytes + rq->bytes > sv->budget) break;
+        fresh_bytes += rq->bytes;
+        fresh.push_back(rq);
+        it = sv->queue.erase(it);
+      }
+      sv->used += fresh_bytes;
+      sv->slots += (int)(fresh.size() + repeats.size() + firsts.size());
+      sv->peak_bytes = std::max<int64_t>(sv->peak_bytes, (int64_t)sv->used);
+    }
+    std::vector<InFlight> launched;
+    if (!fresh.empty()) {
+      std::vector<osqp_problem> probs;
+      for (auto &r : fresh) probs.push_back(r->qp.view());
+      osqp_batch *b = nullptr;
+      int rc = osqp_batch_setup(&b, (int)probs.size(), probs.data(), &sv->set);
+      for (size_t k = 0; rc == OSQP_OK && k < fresh.size(); ++k)
+        if (fresh[k]->qp.has_x || fresh[k]->qp.has_y)
+          rc = osqp_batch_warm_start(b, (int)k, fresh[k]->qp.has_x ? fresh[k]->qp.xws.data() : nullptr,
+                                     fresh[k]->qp.has_y ? fresh[k]->qp.yws.data() : nullptr);
+      if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+      if (rc == OSQP_OK) {
+        InFlight f;
+        f.b = b; f.bytes = fresh_bytes; f.reqs = fresh;
+        launched.push_back(std::move(f));
+      } else {
+        if (b) osqp_batch_cleanup(b);
+        server_fail(sv, fresh, rc, fresh_bytes);
+      }
+    }
+    for (auto &rq : firsts) {
+      osqp_problem p = rq->qp.view();
+      osqp_batch *b = nullptr;
+      int rc = osqp_batch_setup(&b, 1, &p, &sv->set);
+      if (rc == OSQP_OK && (rq->qp.has_x || rq->qp.has_y))
+        rc = osqp_batch_warm_start(b, 0, rq->qp.has_x ? rq->qp.xws.data() : nullptr,
+                                   rq->qp.has_y ? rq->qp.yws.data() : nullptr);
+      if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+      if (rc == OSQP_OK) {
+        {
+          std::lock_guard<std::mutex> g(sv->mu);
+          sv->resident[rq->key].b = b;
+        }
+        InFlight f;
+        f.b = b; f.resident = true; f.key = rq->key; f.reqs = {rq};
+        launched.push_back(std::move(f));
+      } else {
+        if (b) osqp_batch_cleanup(b);
+        {
+          std::lock_guard<std::mutex> g(sv->mu);
+          sv->resident.erase(rq->key);
+        }
+        server_fail(sv, {rq}, rc, rq->bytes);
+      }
+    }
+    for (auto &rq : repeats) {
+      osqp_batch *b;
+      {
+        std::lock_guard<std::mutex> g(sv->mu);
+        b = sv->resident[rq->key].b;
+      }
+      int rc = osqp_batch_update_vectors(b, 0, rq->qp.q.data(), rq->qp.l.data(), rq->qp.u.data());
+      if (rc == OSQP_OK && (rq->qp.has_x || rq->qp.has_y))
+        rc = osqp_batch_warm_start(b, 0, rq->qp.has_x ? rq->qp.xws.data() : nullptr,
+                                   rq->qp.has_y ? rq->qp.yws.data() : nullptr);
+      if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+      if (rc == OSQP_OK) {
+        InFlight f;
+        f.b = b; f.resident = true; f.key = rq->key; f.reqs = {rq};
+        launched.push_back(std::move(f));
+      } else {
+        {
+          std::lock_guard<std::mutex> g(sv->mu);
+          sv->resident[rq->key].busy = false;
+        }
+        server_fail(sv, {rq}, rc, 0);
+      }
+    }
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      sv->batches += (int64_t)launched.size();
+      for (auto &f : launched) sv->inflight.push_back(std::move(f));
+      sv->peak_inflight = std::max<int64_t>(sv->peak_inflight, (int64_t)sv->inflight.size());
+    }
+    // (3) nothing admitted and work on the device: poll again shortly
+    if (launched.empty() && done.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+osqp_int osqp_server_create(osqp_server **out, size_t hbm_budget_bytes, osqp_int max_slots,
+                            const osqp_settings *s) {
+  if (!out) return OSQP_ERR_NOT_SETUP;
+  *out = nullptr;
+  if (max_slots <= 0 || hbm_budget_bytes == 0) return OSQP_ERR_SETTINGS;
+  osqp_settings st;
+  if (s) st = *s; else osqp_set_default_settings(&st);
+  int rc = check_settings(st);
+  if (rc) return rc;
+  if (st.stream) return OSQP_ERR_SETTINGS;   // every micro-batch owns its stream
+  if (osqp_device_count() <= 0) return OSQP_ERR_NO_DEVICE;
+  try {
+    osqp_server *sv = new osqp_server();
+    sv->set = st;
+    sv->budget = hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    sv->worker = std::thread(server_loop, sv);
+    *out = sv;
+  } catch (...) {
+    return OSQP_ERR_ALLOC;
+  }
+  return OSQP_OK;
+}
+
+osqp_int osqp_server_submit(osqp_server *sv, const osqp_problem *p, uint64_t structure_key,
+                            const osqp_float *x_ws, const osqp_float *y_ws, uint64_t *ticket) {
+  if (!sv || !p || !ticket) return OSQP_ERR_NOT_SETUP;
+  int rc = check_problem(*p);
+  if (rc) return rc;
+  try {
+    auto rq = std::make_shared<ServerReq>();
+    rq->qp.copy_from(*p, x_ws, y_ws);
+    rq->key = structure_key;
+    rq->bytes = estimate_bytes(*p, sv->set);
+    if (rq->bytes > sv->budget) return OSQP_ERR_BUDGET;
+    rq->t_submit = now_s();
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (sv->stop) return OSQP_ERR_NOT_SETUP;
+    rq->ticket = sv->next_ticket++;
+    *ticket = rq->ticket;
+    sv->results[rq->ticket] = ServerResult();
+    sv->queue.push_back(rq);
+  } catch (...) {
+    return OSQP_ERR_ALLOC;
+  }
+  sv->cv_work.notify_all();
+  return OSQP_OK;
+}
+
+osqp_int osqp_server_wait(osqp_server *sv, uint64_t ticket, osqp_float *x, osqp_float *y,
+                          osqp_info *info, double *latency_s) {
+  if (!sv) return OSQP_ERR_NOT_SETUP;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->results.find(ticket);
+  if (it == sv->results.end()) return OSQP_ERR_INDEX;
+  sv->cv_done.wait(lk, [&] { return sv->results[ticket].done; });
+  ServerResult r = std::move(sv->results[ticket]);
+  sv->results.erase(ticket);
+  lk.unlock();
+  if (r.rc != OSQP_OK) return r.rc;
+  if (x) std::memcpy(x, r.x.data(), sizeof(double) * r.x.size());
+  if (y && !r.y.empty()) std::memcpy(y, r.y.data(), sizeof(double) * r.y.size());
+  if (info) *info = r.info;
+  if (latency_s) *latency_s = r.latency;
+  return OSQP_OK;
+}
+
+osqp_int osqp_server_stats(const osqp_server *sv, int64_t *completed, int64_t *batches,
+                           int64_t *peak_inflight, int64_t *peak_bytes) {
+  if (!sv) return OSQP_ERR_NOT_SETUP;
+  osqp_server *m = const_cast<osqp_server *>(sv);
+  std::lock_guard<std::mutex> g(m->mu);
+  if (completed) *completed = sv->completed;
+  if (batches) *batches = sv->batches;
+  if (peak_inflight) *peak_inflight = sv->peak_inflight;
+  if (peak_bytes) *peak_bytes = sv->peak_bytes;
+  return OSQP_OK;
+}
+
+void osqp_server_destroy(osqp_server *sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  for (auto &f : sv->inflight) {
+    (void)osqp_batch_sync(f.b);
+    if (!f.resident) osqp_batch_cleanup(f.b);
+  }
+  for (auto &kv : sv->resident)
+    if (kv.second.b) osqp_batch_cleanup(kv.second.b);
+  delete sv;
+}
+
+}  // extern "C"

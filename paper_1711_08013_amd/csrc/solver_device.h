@@ -26,8 +26,11 @@ struct QPView {
   double *a64, *at64, *p64, *q64, *l64, *u64;
   double *D, *E, *Dinv, *Einv;
   const unsigned char *iseq;
-  T *rho, *rhoinv, *minv, *x, *z, *y, *xt, *zt, *r, *d, *p, *w, *t, *s;
+  T *rho, *rhoinv, *minv;
+  double *x, *z, *y, *xt;
+  T *zt, *r, *d, *p, *w, *t, *s;
   double *dx, *dy;
+  double *zt64, *s64;   // A x~ and the step vector in double (alias zt, s in FP64)
   const double *xws, *yws;
   double *xo, *yo, *zo;
   QPState *st;
@@ -54,6 +57,7 @@ struct QPView {
     r = b.r + ds.xo; d = b.d + ds.xo; p = b.p + ds.xo; w = b.w + ds.xo;
     t = b.t + ds.yo; s = b.s + ds.yo;
     dx = b.dx + ds.xo; dy = b.dy + ds.yo;
+    zt64 = b.zt64 + ds.yo; s64 = b.s64 + ds.yo;
     xws = b.xws + ds.xo; yws = b.yws + ds.yo;
     xo = b.xo + ds.xo; yo = b.yo + ds.yo; zo = b.zo + ds.yo;
     st = b.st + k;
@@ -278,11 +282,20 @@ template <class T, class Team>
 __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &set,
                          DenseLDS<T> *dl = nullptr, T *dB = nullptr, bool dense_ok = false) {
   const int n = v.n, m = v.m;
-  const T sigma = T(set.sigma), alpha = T(set.alpha), one_m_alpha = T(1.0 - set.alpha);
+  const T sigma = T(set.sigma);
   const double c = v.st->c, cinv = 1.0 / c;
   double rho_bar = v.st->rho_bar;
+  // rho_i in double for the iterate updates and residuals (the stored T copy
+  // feeds only the PCG products)
+  auto rho_of = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
   const Rows rn(tm, v.ln), rm(tm, v.lm);
   const unsigned long long t_start = wall_clock64();
+  unsigned long long ph = t_start, c_factor = 0, c_pcg = 0, c_update = 0, c_check = 0;
+  auto lap = [&](unsigned long long &acc) {   // phase timer (team leader's clock)
+    const unsigned long long t = wall_clock64();
+    acc += t - ph;
+    ph = t;
+  };
 
   set_rho_and_precond(tm, v, rho_bar, set.sigma);
   // dense preconditioner: reuse the stored factor while rho-bar is unchanged
@@ -291,9 +304,11 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     if (v.dense && dense_ok) {
       use_dense = true;
       if (v.st->factor_rho != rho_bar) {
+        ph = wall_clock64();
         use_dense = form_and_factor<T>(tm, v, *dl, dB, set.sigma);
         if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
         tm.sync();
+        lap(c_factor);
       }
     }
   }
@@ -301,29 +316,32 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   // initial iterate: continue, zeros, or the warm start of Section 6
   const int mode = v.st->init_mode;
   if (mode == 1) {
-    for (int j = tm.tid; j < n; j += tm.nt) { v.x[j] = T(0); v.xt[j] = T(0); }
-    for (int i = tm.tid; i < m; i += tm.nt) { v.z[i] = T(0); v.y[i] = T(0); }
+    for (int j = tm.tid; j < n; j += tm.nt) { v.x[j] = 0.0; v.xt[j] = 0.0; }
+    for (int i = tm.tid; i < m; i += tm.nt) { v.z[i] = 0.0; v.y[i] = 0.0; }
   } else if (mode == 2) {
     for (int j = tm.tid; j < n; j += tm.nt) {
-      const T xv = T(v.Dinv[j] * v.xws[j]);
+      const double xv = v.Dinv[j] * v.xws[j];
       v.x[j] = xv; v.xt[j] = xv;
     }
-    for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = T(c * v.Einv[i] * v.yws[i]);
+    for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = c * v.Einv[i] * v.yws[i];
     tm.sync();
     for (int i = rm.g; i < m; i += rm.ng) {
-      T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.x), rm.L);
+      double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, v.x), rm.L);
       if (rm.lane == 0) v.z[i] = a;
     }
   } else {
     for (int j = tm.tid; j < n; j += tm.nt) v.xt[j] = v.x[j];
   }
   tm.sync();
-  // zt = A xt ; s = rho (z - zt) - y  (feeds the first right-hand side)
+  // zt = A xt ; s = rho (z - zt) - y  (feeds the first right-hand side);
+  // both in double from the double copy of A (a mixed-precision refinement:
+  // each linear solve starts from a residual computed in FP64)
   for (int i = rm.g; i < m; i += rm.ng) {
-    T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.xt), rm.L);
+    double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, v.xt), rm.L);
     if (rm.lane == 0) {
-      v.zt[i] = a;
-      v.s[i] = v.rho[i] * (v.z[i] - a) - v.y[i];
+      v.zt64[i] = a;
+      if (sizeof(T) == 4) v.zt[i] = T(a);
+      v.s64[i] = rho_of(i) * (v.z[i] - a) - v.y[i];
     }
   }
   tm.sync();
@@ -335,6 +353,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   const double floor_rel = sizeof(T) == 4 ? 1e-6 : 1e-12;
   int bad = 0;
 
+  ph = wall_clock64();
   while (true) {
     // --- PCG start: r = b - K xt with b = sigma x - q + A'(rho z - y)
     //     (Section 3.1, indirect method), K = P + sigma I + A' R A, using
@@ -342,13 +361,14 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     double red[2];
     red[0] = 0.0; red[1] = 0.0;
     for (int j = rn.g; j < n; j += rn.ng) {
-      T a = row_partial<T>(v.atrp, v.atci, v.atv, j, rn.lane, rn.L, v.s) -
-            row_partial<T>(v.prp, v.pci, v.pv, j, rn.lane, rn.L, v.xt);
+      double a = row_partial<double>(v.atrp, v.atci, v.at64, j, rn.lane, rn.L, v.s64) -
+                 row_partial<double>(v.prp, v.pci, v.p64, j, rn.lane, rn.L, v.xt);
       a = group_sum(a, rn.L);
       if (rn.lane == 0) {
-        const T rj = sigma * (v.x[j] - v.xt[j]) - v.q[j] + a;
+        const double r64 = set.sigma * (double(v.x[j]) - double(v.xt[j])) - v.q64[j] + a;
+        const T rj = T(r64);
         v.r[j] = rj;
-        red[1] = fmax(red[1], fabs(double(rj)));
+        red[1] = fmax(red[1], fabs(r64));
         if (!use_dense) {
           const T dj = v.minv[j] * rj;
           v.d[j] = dj; v.p[j] = dj;
@@ -399,10 +419,11 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       tm.template reduce<1, 0>(red);
       const double pw = red[0];
       if (!(pw > 0.0) || !isfinite(pw)) { bad |= 1; break; }
-      const T a_step = T(rz / pw);
+      const double a_d = rz / pw;
+      const T a_step = T(a_d);
       red[0] = 0.0; red[1] = 0.0;
       for (int j = tm.tid; j < n; j += tm.nt) {
-        v.xt[j] += a_step * v.p[j];
+        v.xt[j] += a_d * double(v.p[j]);
         const T rj = v.r[j] - a_step * v.w[j];
         v.r[j] = rj;
         red[1] = fmax(red[1], fabs(double(rj)));
@@ -428,30 +449,34 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       if (!(rz > 0.0)) break;
     }
     pcg_total += it;
+    lap(c_pcg);
     ++k;
     const bool do_check = (set.check_every > 0 && k % set.check_every == 0) || k >= set.max_iter;
     // --- Algorithm 1 updates: x relaxed; v = alpha zt + (1-alpha) z + y/rho;
     //     z = Pi(v); y = rho (v - z)  (v-form of Section 3.3)
     for (int j = tm.tid; j < n; j += tm.nt) {
-      const T xn = alpha * v.xt[j] + one_m_alpha * v.x[j];
-      if (do_check) v.dx[j] = double(xn) - double(v.x[j]);
+      const double xn = set.alpha * v.xt[j] + (1.0 - set.alpha) * v.x[j];
+      if (do_check) v.dx[j] = xn - v.x[j];
       v.x[j] = xn;
     }
     for (int i = rm.g; i < m; i += rm.ng) {
-      T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.xt), rm.L);
+      const double a64 =
+          group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, v.xt), rm.L);
       if (rm.lane == 0) {
-        const T zi = v.z[i], yi = v.y[i], ri = v.rho[i];
-        const T vv = alpha * a + one_m_alpha * zi + v.rhoinv[i] * yi;
-        const T zn = fmin(fmax(vv, v.l[i]), v.u[i]);
-        const T yn = ri * (vv - zn);
-        if (do_check) v.dy[i] = double(yn) - double(yi);
-        v.zt[i] = a;
+        const double zi = v.z[i], yi = v.y[i], ri = rho_of(i);
+        const double vv = set.alpha * a64 + (1.0 - set.alpha) * zi + yi / ri;
+        const double zn = fmin(fmax(vv, v.l64[i]), v.u64[i]);
+        const double yn = ri * (vv - zn);
+        if (do_check) v.dy[i] = yn - yi;
+        if (sizeof(T) == 4) v.zt[i] = T(a64);
+        v.zt64[i] = a64;
         v.z[i] = zn;
         v.y[i] = yn;
-        v.s[i] = ri * (zn - a) - yn;
+        v.s64[i] = ri * (zn - a64) - yn;
       }
     }
     tm.sync();
+    lap(c_update);
     if (!do_check) continue;
 
     // --- FP64 termination check (Sections 3.4, 5.1): unscaled residuals
@@ -543,6 +568,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     prs = chk[5]; pnorm = fmax(chk[6], chk[7]);
     drs = chk[12]; dnorm = fmax(chk[13], fmax(chk[14], chk[15]));
     have_check = true;
+    lap(c_check);
     if (res_prim <= eps_prim && res_dual <= eps_dual) { status = 1; break; }
     // primal infeasibility (Section 5.1, strict-sign reading)
     {
@@ -572,10 +598,12 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
           if (v.dense && dense_ok) {
             use_dense = form_and_factor<T>(tm, v, *dl, dB, set.sigma);
             if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
+            tm.sync();
+            lap(c_factor);
           }
         }
         for (int i = tm.tid; i < m; i += tm.nt)
-          v.s[i] = v.rho[i] * (v.z[i] - v.zt[i]) - v.y[i];
+          v.s64[i] = rho_of(i) * (v.z[i] - v.zt64[i]) - v.y[i];
         tm.sync();
       }
     }
@@ -615,6 +643,11 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     S.init_mode = 0;
     S.bad = bad;
     S.solve_ms = double(wall_clock64() - t_start) * set.wall_tick_s * 1e3;
+    const double tk = set.wall_tick_s * 1e3;
+    S.t_factor_ms = double(c_factor) * tk;
+    S.t_pcg_ms = double(c_pcg) * tk;
+    S.t_update_ms = double(c_update) * tk;
+    S.t_check_ms = double(c_check) * tk;
   }
   tm.sync();
 }
