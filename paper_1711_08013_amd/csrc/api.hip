@@ -91,9 +91,10 @@ int check_settings(const osqp_settings &s) {
 }
 
 int pow2_lanes(double avg) {
-  // lanes per row: about half the average row length, a power of two in [1, 64]
+  // lanes per row: about an eighth of the average row length (two four-wide
+  // gather rounds per lane), a power of two in [1, 64]
   int L = 1;
-  while (L < 64 && 2.0 * L < avg) L <<= 1;
+  while (L < 64 && 8.0 * L < avg) L <<= 1;
   return L;
 }
 
@@ -456,7 +457,14 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     d.xo = b->sum_n; d.yo = b->sum_m;
     d.a_rp = b->sum_m + k; d.at_rp = b->sum_n + k; d.p_rp = b->sum_n + k;
     d.a_nz = b->nnz_a; d.at_nz = b->nnz_a; d.p_nz = b->nnz_p;
-    d.lm = pow2_lanes(p.m > 0 ? double(p.A.nnz) / p.m : 1.0);
+    // passes over A take rows with one entry a lane each; the lane count
+    // serves the rows with several entries
+    int64_t multi_nnz = 0, multi_cnt = 0;
+    for (int i = 0; i < p.m; ++i) {
+      const int len = p.A.indptr[i + 1] - p.A.indptr[i];
+      if (len >= 2) { multi_nnz += len; ++multi_cnt; }
+    }
+    d.lm = pow2_lanes(multi_cnt > 0 ? double(multi_nnz) / double(multi_cnt) : 1.0);
     d.ln = pow2_lanes(double(pfull_nnz[k] + p.A.nnz) / p.n);
     d.dense_off = 0;
     b->sum_n += p.n; b->sum_m += p.m; b->nnz_a += p.A.nnz; b->nnz_p += pfull_nnz[k];
@@ -510,14 +518,15 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     int nmax = 0, rmax = 0;
     for (int k : cand) {
       const int n = probs[k].n, ld = (n + 7) & ~7;
-      const double need = (double)n * ld * tsz;
+      const int64_t elems = (int64_t)n * ld + (int64_t)((n + 63) / 64) * 64 * 64;
+      const double need = (double)elems * tsz;
       if (bytes + need > kDenseBudget) break;
       bytes += need;
       QPDesc &d = b->desc[k];
       d.dense = 1;
       d.dld = ld;
       d.dense_off = b->dense_total;
-      b->dense_total += (int64_t)n * ld;
+      b->dense_total += elems;
       nmax = std::max(nmax, n);
       rmax = std::max(rmax, d.mr_cnt);
     }
@@ -684,8 +693,10 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       std::stable_sort(b->polish_list.begin(), b->polish_list.end(),
                        [&](int a, int c) { return probs[a].n > probs[c].n; });
       b->polish_rmax = rmax;
-      b->pws_stride = (long long)nmax * nmax + (long long)rmax * nmax + 3LL * nmax +
-                      5LL * mmax + 64;
+      const long long ldm = (nmax + 7) & ~7;
+      b->pws_stride = (long long)nmax * ldm + (long long)((nmax + 63) / 64) * 64 * 64 +
+                      (long long)rmax * nmax + 3LL * nmax + 5LL * mmax + 64;
+      b->pws_stride = (b->pws_stride + 7) & ~7LL;   // 64-byte slot bases (16-byte loads)
       b->polish_slots = std::max(1, std::min((int)b->polish_list.size(),
                                              prop.multiProcessorCount));
       if (hipMalloc(&b->d_pws, sizeof(double) * b->pws_stride * b->polish_slots) != hipSuccess ||

@@ -26,7 +26,10 @@ struct DenseLDS {
       T pb[kTS][kNB + 1];
       T diag[kNB][kNB + 1];
     };
-    T blk[64][65];   // diagonal block of a triangular solve
+    struct {
+      T blk[64][65];   // a diagonal block of L
+      T xs[64][65];    // its inverse, row by row
+    };
   };
   T ys[64];
   int flag;
@@ -158,23 +161,36 @@ __device__ __forceinline__ bool dense_cholesky(const WGTeam &tm, DenseLDS<T> &s,
       s.diag[r][c] = (r < nb && c <= r) ? M[(size_t)(kb + r) * ld + kb + c] : T(0);
     }
     tm.sync();
-    for (int c = 0; c < nb; ++c) {
-      if (tm.tid == 0) {
-        const T piv = s.diag[c][c];
-        if (!(piv > T(0)) || !isfinite(double(piv))) s.flag = 1;
-        s.diag[c][c] = piv > T(0) ? T(sqrt(double(piv))) : T(1);
+    // wave 0 factors the block in registers: lane r holds row r
+    if (tm.tid < kWave) {
+      const int r = tm.tid;
+      T row[kNB];
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) row[c] = (r < nb && c <= r) ? s.diag[r][c] : T(0);
+      bool bad = false;
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        if (c < nb) {
+          const T piv = __shfl(row[c], c, kWave);
+          bad |= !(piv > T(0)) || !isfinite(double(piv));
+          const T d = piv > T(0) ? T(sqrt(double(piv))) : T(1);
+          if (r == c) row[c] = d;
+          else if (r > c) row[c] = row[c] / d;
+#pragma unroll
+          for (int q = c + 1; q < kNB; ++q) {
+            const T lqc = __shfl(row[c], q, kWave);
+            if (q < nb && r >= q) row[q] -= row[c] * lqc;
+          }
+        }
       }
-      tm.sync();
-      const T dc = s.diag[c][c];
-      for (int r = c + 1 + tm.tid; r < nb; r += tm.nt) s.diag[r][c] /= dc;
-      tm.sync();
-      const int w = nb - c - 1;
-      for (int e = tm.tid; e < w * w; e += tm.nt) {
-        const int r = c + 1 + e / w, q = c + 1 + e % w;
-        if (q <= r) s.diag[r][q] -= s.diag[r][c] * s.diag[q][c];
+      if (r < nb) {
+#pragma unroll
+        for (int c = 0; c < kNB; ++c)
+          if (c <= r) s.diag[r][c] = row[c];
       }
-      tm.sync();
+      if (r == 0 && bad) s.flag = 1;
     }
+    tm.sync();
     for (int e = tm.tid; e < nb * nb; e += tm.nt) {
       const int r = e / nb, c = e % nb;
       if (c <= r) M[(size_t)(kb + r) * ld + kb + c] = s.diag[r][c];
@@ -213,69 +229,147 @@ __device__ __forceinline__ bool dense_cholesky(const WGTeam &tm, DenseLDS<T> &s,
   return ok;
 }
 
-constexpr int kSB = 64;   // triangular-solve block (one wave solves a block)
+constexpr int kSB = 64;   // triangular-solve block
 
-// Solve L L' x = b in place (b -> x); L lower, row-major (ld).  Each 64-row
-// block is solved by wave 0 in registers (shuffle broadcasts), the rest of
-// the workgroup applies the block to the remaining rows; the forward sweep
-// reads L by row chunks, the backward sweep by coalesced column chunks, so
-// each sweep reads the lower triangle once.
+// Inverses of the 64 x 64 diagonal blocks of L (row-major, lower), stored as
+// nblk consecutive 64 x 64 row-major blocks in Linv (zero above the
+// diagonal).  Wave 0 forms each inverse row by row in LDS: row r of X = L_kk^-1
+// is (e_r - sum_{q<r} L_rq X_q) / L_rr, one column per lane.
 template <class T>
-__device__ __forceinline__ void dense_solve_llt(const WGTeam &tm, DenseLDS<T> &s, const T *L, int ld, int n,
-                                T *x) {
+__device__ __forceinline__ void dense_invert_diag(const WGTeam &tm, DenseLDS<T> &s, const T *L,
+                                                  int ld, int n, T *Linv) {
+  const int nblk = (n + kSB - 1) / kSB;
   const int lane = tm.tid & (kWave - 1);
-  const bool w0 = tm.tid < kWave;
-  // forward: L y = b
-  for (int kb = 0; kb < n; kb += kSB) {
-    const int nb = min(kSB, n - kb);
-    for (int e = tm.tid; e < nb * kSB; e += tm.nt) {
+  for (int bk = 0; bk < nblk; ++bk) {
+    const int kb = bk * kSB, nb = min(kSB, n - kb);
+    for (int e = tm.tid; e < kSB * kSB; e += tm.nt) {
       const int r = e / kSB, c = e % kSB;
-      s.blk[r][c] = (c <= r && c < nb) ? L[(size_t)(kb + r) * ld + kb + c] : T(0);
+      // padded rows/columns beyond nb: identity, so the padded inverse is too
+      s.blk[r][c] = (r < nb && c <= r) ? L[(size_t)(kb + r) * ld + kb + c]
+                                        : (r == c ? T(1) : T(0));
     }
     tm.sync();
-    if (w0) {
-      T br = lane < nb ? x[kb + lane] : T(0);
-      for (int c = 0; c < nb; ++c) {
-        const T lrc = lane < nb ? s.blk[lane][c] : T(0);
-        const T yc = __shfl(lane == c ? br / lrc : T(0), c, kWave);
-        if (lane == c) br = yc;
-        else if (lane > c) br -= lrc * yc;
+    if (tm.tid < kWave) {
+      const int c = lane;
+      for (int r = 0; r < kSB; ++r) {
+        T v = (r == c) ? T(1) : T(0);
+        for (int q = c; q < r; ++q) v -= s.blk[r][q] * s.xs[q][c];
+        s.xs[r][c] = (c <= r) ? v / s.blk[r][r] : T(0);
       }
-      if (lane < nb) { x[kb + lane] = br; s.ys[lane] = br; }
     }
     tm.sync();
-    for (int i = kb + nb + tm.tid; i < n; i += tm.nt) {
-      const T *r = L + (size_t)i * ld + kb;
+    T *dst = Linv + (size_t)bk * kSB * kSB;
+    for (int e = tm.tid; e < kSB * kSB; e += tm.nt) dst[e] = s.xs[e / kSB][e % kSB];
+    tm.sync();
+  }
+}
+
+// Four consecutive T from a 16-byte-aligned address.
+template <class T>
+__device__ __forceinline__ void load4(const T *p, T &a, T &b, T &c, T &d) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    a = v.x; b = v.y; c = v.z; d = v.w;
+  } else {
+    const double2 v0 = *reinterpret_cast<const double2 *>(p);
+    const double2 v1 = *reinterpret_cast<const double2 *>(p + 2);
+    a = v0.x; b = v0.y; c = v1.x; d = v1.y;
+  }
+}
+
+// Solve L L' x = b in place (b -> x); L lower, row-major (ld a multiple of 8),
+// Linv the inverted diagonal blocks.  Per 64-row block: the block unknowns
+// are a 64 x 64 matrix-vector product with the block inverse (parallel), then
+// the rest of the workgroup's rows / columns are updated.  The forward sweep
+// reads L by 64-wide row chunks (16 lanes per row, 16-byte loads, several
+// rows in flight), the backward sweep by column quads (64 rows in flight per
+// lane), so each sweep reads the lower triangle once.
+template <class T>
+__device__ __forceinline__ void dense_solve_llt(const WGTeam &tm, DenseLDS<T> &s, const T *L,
+                                                int ld, int n, const T *Linv, T *x) {
+  const int nblk = (n + kSB - 1) / kSB;
+  // ---- forward: L y = b
+  for (int bk = 0; bk < nblk; ++bk) {
+    const int kb = bk * kSB, nb = min(kSB, n - kb);
+    const T *Bi = Linv + (size_t)bk * kSB * kSB;
+    // y_blk = Linv_kk b_blk: 4 lanes per row, 16 columns each
+    for (int t = tm.tid; t < kSB * 4; t += tm.nt) {
+      const int r = t >> 2, part = t & 3;
       T acc = T(0);
-      for (int c = 0; c < nb; ++c) acc += r[c] * s.ys[c];
-      x[i] -= acc;
+      if (r < nb) {
+#pragma unroll
+        for (int c4 = 0; c4 < 16; c4 += 4) {
+          const int c = part * 16 + c4;
+          T a0, a1, a2, a3;
+          load4(Bi + r * kSB + c, a0, a1, a2, a3);
+          acc += (c + 0 < nb ? a0 * x[kb + c + 0] : T(0)) + (c + 1 < nb ? a1 * x[kb + c + 1] : T(0)) +
+                 (c + 2 < nb ? a2 * x[kb + c + 2] : T(0)) + (c + 3 < nb ? a3 * x[kb + c + 3] : T(0));
+        }
+      }
+      acc = group_sum(acc, 4);
+      if (part == 0) s.ys[r] = acc;
+    }
+    tm.sync();
+    for (int r = tm.tid; r < nb; r += tm.nt) x[kb + r] = s.ys[r];
+    // rows below: b_i -= L[i, kb:kb+64] y_blk (only when a full block is above)
+    if (kb + nb < n) {
+      const int sub = tm.tid & 15, grp = tm.tid >> 4, ngrp = tm.nt >> 4;
+      const T y0 = s.ys[4 * sub], y1 = s.ys[4 * sub + 1], y2 = s.ys[4 * sub + 2],
+              y3 = s.ys[4 * sub + 3];
+      constexpr int U = 4;
+      for (int i0 = kb + nb + grp; i0 < n; i0 += ngrp * U) {
+        T part[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * ngrp;
+          part[u] = T(0);
+          if (i < n) {
+            T a0, a1, a2, a3;
+            load4(L + (size_t)i * ld + kb + 4 * sub, a0, a1, a2, a3);
+            part[u] = a0 * y0 + a1 * y1 + a2 * y2 + a3 * y3;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const T v = group_sum(part[u], 16);
+          const int i = i0 + u * ngrp;
+          if (sub == 0 && i < n) x[i] -= v;
+        }
+      }
     }
     tm.sync();
   }
-  // backward: L' x = y
-  const int nblk = (n + kSB - 1) / kSB;
+  // ---- backward: L' x = y
   for (int bk = nblk - 1; bk >= 0; --bk) {
     const int kb = bk * kSB, nb = min(kSB, n - kb);
-    for (int e = tm.tid; e < nb * kSB; e += tm.nt) {
-      const int r = e / kSB, c = e % kSB;
-      s.blk[r][c] = (c <= r && c < nb) ? L[(size_t)(kb + r) * ld + kb + c] : T(0);
-    }
-    tm.sync();
-    if (w0) {
-      T bs = lane < nb ? x[kb + lane] : T(0);
-      for (int r = nb - 1; r >= 0; --r) {
-        const T lrs = lane < nb ? s.blk[r][lane] : T(0);   // L[r][lane]
-        const T xr = __shfl(lane == r ? bs / lrs : T(0), r, kWave);
-        if (lane == r) bs = xr;
-        else if (lane < r) bs -= lrs * xr;
-      }
-      if (lane < nb) { x[kb + lane] = bs; s.ys[lane] = bs; }
-    }
-    tm.sync();
-    for (int j = tm.tid; j < kb; j += tm.nt) {
+    const T *Bi = Linv + (size_t)bk * kSB * kSB;
+    // x_blk = Linv_kk' y_blk: x_c = sum_{r >= c} Linv[r][c] y_r
+    for (int t = tm.tid; t < kSB * 4; t += tm.nt) {
+      const int c = t >> 2, part = t & 3;
       T acc = T(0);
-      for (int r = 0; r < nb; ++r) acc += L[(size_t)(kb + r) * ld + j] * s.ys[r];
-      x[j] -= acc;
+      if (c < nb) {
+        for (int r = part * 16; r < part * 16 + 16; ++r)
+          if (r >= c && r < nb) acc += Bi[r * kSB + c] * x[kb + r];
+      }
+      acc = group_sum(acc, 4);
+      if (part == 0) s.ys[c] = acc;
+    }
+    tm.sync();
+    for (int r = tm.tid; r < nb; r += tm.nt) x[kb + r] = s.ys[r];
+    // columns to the left: x_j -= sum_r L[kb+r, j] x_{kb+r}, j < kb, four
+    // columns per thread, the 64 rows' loads in flight together
+    for (int j = 4 * tm.tid; j < kb; j += 4 * tm.nt) {
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+#pragma unroll 16
+      for (int r = 0; r < kSB; ++r) {
+        if (r < nb) {
+          T l0, l1, l2, l3;
+          load4(L + (size_t)(kb + r) * ld + j, l0, l1, l2, l3);
+          const T yr = s.ys[r];
+          a0 += l0 * yr; a1 += l1 * yr; a2 += l2 * yr; a3 += l3 * yr;
+        }
+      }
+      x[j] -= a0; x[j + 1] -= a1; x[j + 2] -= a2; x[j + 3] -= a3;
     }
     tm.sync();
   }

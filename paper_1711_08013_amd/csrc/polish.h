@@ -33,8 +33,11 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   const double delta = set.delta, dinv = 1.0 / delta;
   const double c = v.st->c, cinv = 1.0 / c;
   const unsigned long long t0 = wall_clock64();
-  double *M = ws;                                  // n x n
-  double *B = M + (size_t)n * n;                   // rmax x n
+  const int ldm = (n + 7) & ~7;                    // row stride of M (16-byte rows)
+  const int nblk = (n + kSB - 1) / kSB;
+  double *M = ws;                                  // n x ldm
+  double *Minv = M + (size_t)n * ldm;              // nblk inverted 64 x 64 diagonal blocks
+  double *B = Minv + (size_t)nblk * kSB * kSB;     // rmax x n
   double *act = B + (size_t)rmax * n;              // m: -1, 0, +1
   double *bact = act + m;                          // m
   double *tx = bact + m, *ty = tx + n;             // n, m
@@ -56,28 +59,29 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] >= 2) multi[R++] = i;
     R_sh = R;
   }
-  for (size_t e = tm.tid; e < (size_t)n * n; e += tm.nt) M[e] = 0.0;
+  for (size_t e = tm.tid; e < (size_t)n * ldm; e += tm.nt) M[e] = 0.0;
   tm.sync();
   const int R = min(R_sh, rmax);
   for (size_t e = tm.tid; e < (size_t)R * n; e += tm.nt) B[e] = 0.0;
   tm.sync();
   // P + d I, plus the single-entry active rows on the diagonal
   for (int j = tm.tid; j < n; j += tm.nt) {
-    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) M[(size_t)j * n + v.pci[k]] = v.p64[k];
+    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) M[(size_t)j * ldm + v.pci[k]] = v.p64[k];
     double dsum = delta;
     for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
       const int i = v.atci[k];
       if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] == 1) dsum += v.at64[k] * v.at64[k] * dinv;
     }
-    M[(size_t)j * n + j] += dsum;
+    M[(size_t)j * ldm + j] += dsum;
   }
   for (int r = tm.tid; r < R; r += tm.nt) {
     const int i = multi[r];
     for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) B[(size_t)r * n + v.aci[k]] = v.a64[k];
   }
   tm.sync();
-  dense_syrk_tn<double>(tm, s, M, n, B, n, R, n, dinv);
-  const bool ok_fact = dense_cholesky<double>(tm, s, M, n, n) && R_sh <= rmax;
+  dense_syrk_tn<double>(tm, s, M, ldm, B, n, R, n, dinv);
+  const bool ok_fact = dense_cholesky<double>(tm, s, M, ldm, n) && R_sh <= rmax;
+  if (ok_fact) dense_invert_diag<double>(tm, s, M, ldm, n, Minv);
   if (!ok_fact) {
     if (tm.tid == 0) v.st->polish_status = -1;
     tm.sync();
@@ -93,7 +97,7 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     g[j] = -v.q64[j] + a * dinv;
   }
   tm.sync();
-  dense_solve_llt<double>(tm, s, M, n, n, g);
+  dense_solve_llt<double>(tm, s, M, ldm, n, Minv, g);
   for (int j = tm.tid; j < n; j += tm.nt) tx[j] = g[j];
   tm.sync();
   for (int i = tm.tid; i < m; i += tm.nt) {
@@ -124,7 +128,7 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       g[j] = rx[j] + a * dinv;
     }
     tm.sync();
-    dense_solve_llt<double>(tm, s, M, n, n, g);
+    dense_solve_llt<double>(tm, s, M, ldm, n, Minv, g);
     for (int i = tm.tid; i < m; i += tm.nt) {
       double a = 0.0;
       if (act[i] != 0.0)
@@ -148,7 +152,10 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     red[1] = fmax(red[1], fabs(e * (ax - z)));
     red[2] = fmax(red[2], fabs(e * ax));
     red[3] = fmax(red[3], fabs(e * z));
-    if ((act[i] < 0.0 && ty[i] > 0.0) || (act[i] > 0.0 && ty[i] < 0.0)) red[8] = 1.0;
+    // sign flag folded in with fmax (a conditional store of the constant
+    // was dropped by hipcc's backend in this loop)
+    const bool flip = (act[i] < 0.0 && ty[i] > 0.0) || (act[i] > 0.0 && ty[i] < 0.0);
+    red[8] = fmax(red[8], flip ? 1.0 : 0.0);
   }
   for (int j = tm.tid; j < n; j += tm.nt) {
     double px = 0.0, aty = 0.0;

@@ -35,6 +35,7 @@ struct QPView {
   double *xo, *yo, *zo;
   QPState *st;
   T *L;              // dense factor (row-major, lower), when dense
+  T *Linv;           // inverses of its 64 x 64 diagonal blocks (after L)
   int ld, dense, mr_cnt;
   const int *mrows;
 
@@ -63,6 +64,7 @@ struct QPView {
     st = b.st + k;
     dense = ds.dense; ld = ds.dld; mr_cnt = ds.mr_cnt;
     L = ds.dense ? b.dmat + ds.dense_off : nullptr;
+    Linv = ds.dense ? L + (size_t)ds.n * ds.dld : nullptr;
     mrows = b.mrows + ds.mr_off;
   }
 };
@@ -77,13 +79,32 @@ struct Rows {
 };
 
 // Partial dot of CSR row r with x over the lanes of a group (not reduced).
+// Four entries per lane are gathered per round so that their loads are in
+// flight together.
 template <class A, class V, class X>
 __device__ __forceinline__ A row_partial(const int *rp, const int *ci, const V *v, int r,
                                          int lane, int L, const X *x) {
-  A s = A(0);
+  A s0 = A(0), s1 = A(0), s2 = A(0), s3 = A(0);
   const int e = rp[r + 1];
-  for (int k = rp[r] + lane; k < e; k += L) s += A(v[k]) * A(x[ci[k]]);
-  return s;
+  int k = rp[r] + lane;
+  for (; k + 3 * L < e; k += 4 * L) {
+    const int c0 = ci[k], c1 = ci[k + L], c2 = ci[k + 2 * L], c3 = ci[k + 3 * L];
+    const A a0 = A(v[k]), a1 = A(v[k + L]), a2 = A(v[k + 2 * L]), a3 = A(v[k + 3 * L]);
+    s0 += a0 * A(x[c0]); s1 += a1 * A(x[c1]); s2 += a2 * A(x[c2]); s3 += a3 * A(x[c3]);
+  }
+  for (; k < e; k += L) s0 += A(v[k]) * A(x[ci[k]]);
+  return (s0 + s1) + (s2 + s3);
+}
+
+// A pass over the rows of A: rows with at most one entry take one lane each,
+// the rows with several entries (the list mrows) a group of rm.L lanes.
+// body(i, lane, L) reduces over its L lanes; lane 0 holds the result.
+template <class T, class Team, class Body>
+__device__ __forceinline__ void for_a_rows(const Team &tm, const QPView<T> &v, const Rows &rm,
+                                           Body &&body) {
+  for (int i = tm.tid; i < v.m; i += tm.nt)
+    if (v.arp[i + 1] - v.arp[i] <= 1) body(i, 0, 1);
+  for (int r = rm.g; r < v.mr_cnt; r += rm.ng) body(v.mrows[r], rm.lane, rm.L);
 }
 
 __device__ __forceinline__ double clamp_norm(double v) {
@@ -121,13 +142,13 @@ __device__ __forceinline__ void scale_qp(const Team &tm, const QPView<T> &v, con
       a = group_max(a, rn.L) * v.D[j];
       if (rn.lane == 0) v.dx[j] = 1.0 / sqrt(clamp_norm(a));
     }
-    for (int i = rm.g; i < m; i += rm.ng) {
+    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
       double a = 0.0;
-      for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L)
+      for (int k = v.arp[i] + lane; k < v.arp[i + 1]; k += L)
         a = fmax(a, fabs(v.araw[k]) * v.D[v.aci[k]]);
-      a = group_max(a, rm.L) * v.E[i];
-      if (rm.lane == 0) v.dy[i] = 1.0 / sqrt(clamp_norm(a));
-    }
+      a = group_max(a, L) * v.E[i];
+      if (lane == 0) v.dy[i] = 1.0 / sqrt(clamp_norm(a));
+    });
     tm.sync();
     for (int j = tm.tid; j < n; j += tm.nt) v.D[j] *= v.dx[j];
     for (int i = tm.tid; i < m; i += tm.nt) v.E[i] *= v.dy[i];
@@ -262,7 +283,9 @@ __device__ __forceinline__ bool form_and_factor(const WGTeam &tm, const QPView<T
   }
   tm.sync();
   dense_syrk_tn<T>(tm, s, v.L, ld, B, n, R, n, T(1));
-  return dense_cholesky<T>(tm, s, v.L, ld, n);
+  const bool ok = dense_cholesky<T>(tm, s, v.L, ld, n);
+  if (ok) dense_invert_diag<T>(tm, s, v.L, ld, n, v.Linv);
+  return ok;
 }
 
 // d = (L L')^-1 r
@@ -271,7 +294,7 @@ __device__ __forceinline__ void precondition_dense(const WGTeam &tm, const QPVie
   tm.sync();
   for (int j = tm.tid; j < v.n; j += tm.nt) v.d[j] = v.r[j];
   tm.sync();
-  dense_solve_llt<T>(tm, s, v.L, v.ld, v.n, v.d);
+  dense_solve_llt<T>(tm, s, v.L, v.ld, v.n, v.Linv, v.d);
 }
 
 // ------------------------------------------------------------------------
@@ -325,10 +348,10 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     }
     for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = c * v.Einv[i] * v.yws[i];
     tm.sync();
-    for (int i = rm.g; i < m; i += rm.ng) {
-      double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, v.x), rm.L);
-      if (rm.lane == 0) v.z[i] = a;
-    }
+    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
+      const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, lane, L, v.x), L);
+      if (lane == 0) v.z[i] = a;
+    });
   } else {
     for (int j = tm.tid; j < n; j += tm.nt) v.xt[j] = v.x[j];
   }
@@ -336,14 +359,14 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   // zt = A xt ; s = rho (z - zt) - y  (feeds the first right-hand side);
   // both in double from the double copy of A (a mixed-precision refinement:
   // each linear solve starts from a residual computed in FP64)
-  for (int i = rm.g; i < m; i += rm.ng) {
-    double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, v.xt), rm.L);
-    if (rm.lane == 0) {
+  for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
+    const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, lane, L, v.xt), L);
+    if (lane == 0) {
       v.zt64[i] = a;
       if (sizeof(T) == 4) v.zt[i] = T(a);
       v.s64[i] = rho_of(i) * (v.z[i] - a) - v.y[i];
     }
-  }
+  });
   tm.sync();
 
   int k = 0, status = 6 /* unsolved */, pcg_total = 0, rho_updates = 0;
@@ -352,6 +375,10 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   double res_prim = 0.0, res_dual = 0.0, eps_prim = 0.0, eps_dual = 0.0;
   const double floor_rel = sizeof(T) == 4 ? 1e-6 : 1e-12;
   int bad = 0;
+  auto pcg_tol = [&](double b0) -> double {
+    return have_check ? fmax(set.pcg_tol_frac * fmin(prs, drs), floor_rel * fmax(dnorm, 1e-30))
+                      : 1e-3 * b0;
+  };
 
   ph = wall_clock64();
   while (true) {
@@ -376,32 +403,41 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         }
       }
     }
+    // the dense preconditioner is a factor of K itself: it is applied only
+    // while the residual misses the tolerance (the PCG iterates are the same)
+    bool dense_skip = false;
     if constexpr (std::is_same<Team, WGTeam>::value) {
       if (use_dense) {
-        precondition_dense(tm, v, *dl);
-        for (int j = tm.tid; j < n; j += tm.nt) {
-          const T dj = v.d[j];
-          v.p[j] = dj;
-          red[0] += double(v.r[j] * dj);
+        tm.template reduce<0, 1>(red + 1);
+        dense_skip = bnorm >= 0.0 && red[1] <= pcg_tol(bnorm);
+        if (!dense_skip) {
+          precondition_dense(tm, v, *dl);
+          for (int j = tm.tid; j < n; j += tm.nt) {
+            const T dj = v.d[j];
+            v.p[j] = dj;
+            red[0] += double(v.r[j] * dj);
+          }
+          tm.template reduce<1, 0>(red);
         }
+      } else {
+        tm.template reduce<1, 1>(red);
       }
+    } else {
+      tm.template reduce<1, 1>(red);
     }
-    tm.template reduce<1, 1>(red);
     double rz = red[0], rinf = red[1];
     if (bnorm < 0.0) bnorm = rinf;
     // inner tolerance (reading): kappa * min(prim, dual residual) of the last
     // check, floored relative to the dual normaliser; 1e-3 of the first
     // residual before the first check
-    double tol = have_check
-                     ? fmax(set.pcg_tol_frac * fmin(prs, drs), floor_rel * fmax(dnorm, 1e-30))
-                     : 1e-3 * bnorm;
+    const double tol = pcg_tol(bnorm);
     int it = 0;
-    while (rinf > tol && it < set.pcg_max_iter) {
+    while (!dense_skip && rinf > tol && it < set.pcg_max_iter) {
       // t = R A p
-      for (int i = rm.g; i < m; i += rm.ng) {
-        T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, rm.lane, rm.L, v.p), rm.L);
-        if (rm.lane == 0) v.t[i] = v.rho[i] * a;
-      }
+      for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
+        const T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, lane, L, v.p), L);
+        if (lane == 0) v.t[i] = v.rho[i] * a;
+      });
       tm.sync();
       // w = P p + sigma p + A' t ; p'w
       red[0] = 0.0;
@@ -433,13 +469,23 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
           red[0] += double(rj * dj);
         }
       }
+      bool converged = false;
       if constexpr (std::is_same<Team, WGTeam>::value) {
         if (use_dense) {
-          precondition_dense(tm, v, *dl);
-          for (int j = tm.tid; j < n; j += tm.nt) red[0] += double(v.r[j] * v.d[j]);
+          tm.template reduce<0, 1>(red + 1);
+          converged = red[1] <= tol;
+          if (!converged) {
+            precondition_dense(tm, v, *dl);
+            for (int j = tm.tid; j < n; j += tm.nt) red[0] += double(v.r[j] * v.d[j]);
+            tm.template reduce<1, 0>(red);
+          }
+        } else {
+          tm.template reduce<1, 1>(red);
         }
+      } else {
+        tm.template reduce<1, 1>(red);
       }
-      tm.template reduce<1, 1>(red);
+      if (converged) { ++it; break; }
       const T beta = T(red[0] / rz);
       rz = red[0];
       rinf = red[1];
@@ -459,10 +505,10 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       if (do_check) v.dx[j] = xn - v.x[j];
       v.x[j] = xn;
     }
-    for (int i = rm.g; i < m; i += rm.ng) {
+    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
       const double a64 =
-          group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, v.xt), rm.L);
-      if (rm.lane == 0) {
+          group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, lane, L, v.xt), L);
+      if (lane == 0) {
         const double zi = v.z[i], yi = v.y[i], ri = rho_of(i);
         const double vv = set.alpha * a64 + (1.0 - set.alpha) * zi + yi / ri;
         const double zn = fmin(fmax(vv, v.l64[i]), v.u64[i]);
@@ -474,7 +520,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         v.y[i] = yn;
         v.s64[i] = ri * (zn - a64) - yn;
       }
-    }
+    });
     tm.sync();
     lap(c_update);
     if (!do_check) continue;
@@ -491,17 +537,17 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     double chk[25];
 #pragma unroll
     for (int kk = 0; kk < 25; ++kk) chk[kk] = 0.0;
-    for (int i = rm.g; i < m; i += rm.ng) {
+    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
       double ax = 0.0, adx = 0.0;
-      for (int kq = v.arp[i] + rm.lane; kq < v.arp[i + 1]; kq += rm.L) {
+      for (int kq = v.arp[i] + lane; kq < v.arp[i + 1]; kq += L) {
         const double a = v.a64[kq];
         const int cj = v.aci[kq];
         ax += a * double(v.x[cj]);
         adx += a * v.dx[cj];
       }
-      ax = group_sum(ax, rm.L);
-      adx = group_sum(adx, rm.L);
-      if (rm.lane == 0) {
+      ax = group_sum(ax, L);
+      adx = group_sum(adx, L);
+      if (lane == 0) {
         const double zi = double(v.z[i]), ei = v.Einv[i];
         chk[2] = fmax(chk[2], fabs(ei * (ax - zi)));
         chk[3] = fmax(chk[3], fabs(ei * ax));
@@ -513,18 +559,20 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         chk[16] = fmax(chk[16], fabs(v.E[i] * dyi));
         // reading: only dy_i > 0 meets u_i and only dy_i < 0 meets l_i; an
         // infinite bound met this way fails the test
-        if (dyi > 0.0) {
-          if (isinf(v.u64[i])) chk[18] = 1.0; else chk[0] += v.u64[i] * dyi;
-        } else if (dyi < 0.0) {
-          if (isinf(v.l64[i])) chk[18] = 1.0; else chk[0] += v.l64[i] * dyi;
-        }
+        // (flags are folded in with fmax/select, not by a conditional store
+        // of a constant: hipcc's backend was seen to drop such stores into
+        // a per-thread reduction array inside a divergent loop)
+        const double bnd = dyi > 0.0 ? v.u64[i] : (dyi < 0.0 ? v.l64[i] : 0.0);
+        const bool hit = isinf(bnd);
+        chk[18] = fmax(chk[18], hit ? 1.0 : 0.0);
+        chk[0] += hit ? 0.0 : bnd * dyi;
         const double wv = ei * adx;
         const bool lf = !isinf(v.l64[i]), uf = !isinf(v.u64[i]);
-        if (lf && uf) chk[21] = fmax(chk[21], fabs(wv));
-        else if (lf) chk[22] = fmax(chk[22], -wv);
-        else if (uf) chk[23] = fmax(chk[23], wv);
+        chk[21] = fmax(chk[21], (lf && uf) ? fabs(wv) : 0.0);
+        chk[22] = fmax(chk[22], (lf && !uf) ? -wv : 0.0);
+        chk[23] = fmax(chk[23], (!lf && uf) ? wv : 0.0);
       }
-    }
+    });
     for (int j = rn.g; j < n; j += rn.ng) {
       double px = 0.0, pdx = 0.0, aty = 0.0, atdy = 0.0;
       for (int kq = v.prp[j] + rn.lane; kq < v.prp[j + 1]; kq += rn.L) {
