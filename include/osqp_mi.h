@@ -53,9 +53,14 @@ typedef double osqp_float;
 #define OSQP_PRECISION_FP64 0       /* every step in double                  */
 #define OSQP_PRECISION_FP32_MIXED 1 /* SpMV/PCG/updates in float; scaling,
                                        checks, certificates, polish in double */
-#define OSQP_LINSYS_AUTO 0          /* dense factor for tiny QPs, else PCG    */
+#define OSQP_LINSYS_AUTO 0          /* low-rank form (P diagonal, few multi-   */
+                                    /* entry rows of A), else the dense factor */
+                                    /* for n <= 2500, else Jacobi PCG          */
 #define OSQP_LINSYS_PCG 1           /* reduced system, Section 3.1 indirect   */
 #define OSQP_LINSYS_DENSE 2         /* dense Cholesky of the reduced matrix   */
+#define OSQP_LINSYS_LOWRANK 3       /* P diagonal, few multi-entry rows of A:  */
+                                    /* Woodbury form of the reduced matrix,    */
+                                    /* else as AUTO                            */
 
 /* Compressed sparse rows.  indptr has nrows+1 entries, indptr[0] = 0,
  * non-decreasing, indptr[nrows] = nnz; each row's column indices strictly
@@ -107,6 +112,8 @@ typedef struct {
   osqp_int pcg_iter;       /* total inner PCG iterations                     */
   osqp_int rho_updates;
   osqp_int polish_status;  /* 1 accepted, -1 rejected, 0 not run            */
+  osqp_int linsys;         /* reduced-system path assigned at setup:         */
+                           /* OSQP_LINSYS_PCG (Jacobi), _DENSE or _LOWRANK   */
   osqp_float obj_val;      /* 1/2 x'Px + q'x on the original data (FP64)    */
   osqp_float prim_res, dual_res, eps_prim, eps_dual; /* unscaled, FP64, Sections 3.4/5.1 */
   osqp_float rho_bar;      /* final rho-bar                                  */

@@ -22,7 +22,7 @@ ERRORS = {0: "ok", 1: "dim", 2: "csr", 3: "p_not_upper", 4: "data_nonfinite", 5:
           6: "settings", 7: "alloc", 8: "budget", 9: "device", 10: "not_setup",
           11: "index", 12: "no_device"}
 PRECISION = {"fp64": 0, "fp32": 1}
-LINSYS = {"auto": 0, "pcg": 1, "dense": 2}
+LINSYS = {"auto": 0, "pcg": 1, "dense": 2, "lowrank": 3}
 
 # every function the header declares (the CPU tests check the exports)
 EXPORTS = [
@@ -69,7 +69,7 @@ class _Settings(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in
-                ("status", "iter", "pcg_iter", "rho_updates", "polish_status")] + \
+                ("status", "iter", "pcg_iter", "rho_updates", "polish_status", "linsys")] + \
                [(k, ctypes.c_double) for k in
                 ("obj_val", "prim_res", "dual_res", "eps_prim", "eps_dual", "rho_bar",
                  "setup_time", "solve_time", "polish_time", "factor_time", "pcg_time",

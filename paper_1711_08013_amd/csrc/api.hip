@@ -24,6 +24,9 @@ constexpr int kPolishMaxN = 3000;   // largest n polished with a dense condensed
 constexpr int kDenseMaxN = 4096;    // largest n that may use the dense preconditioner
 constexpr int kDenseAutoN = 2500;   // largest n given the dense preconditioner by default
 constexpr double kDenseBudget = 48e9;   // bytes of dense factors per batch
+constexpr int kLowRankMaxR = 2048;      // most multi-entry rows of a low-rank QP
+constexpr int64_t kLowRankMaxG = int64_t(1) << 23;   // doubles of G scratch per workgroup
+constexpr double kLowRankBudget = 32e9;   // bytes of low-rank blocks per batch
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -84,7 +87,7 @@ int check_settings(const osqp_settings &s) {
     return OSQP_ERR_SETTINGS;
   if (s.precision != OSQP_PRECISION_FP64 && s.precision != OSQP_PRECISION_FP32_MIXED)
     return OSQP_ERR_SETTINGS;
-  if (s.linsys < 0 || s.linsys > 2) return OSQP_ERR_SETTINGS;
+  if (s.linsys < 0 || s.linsys > 3) return OSQP_ERR_SETTINGS;
   if (s.block_size != 0 && (s.block_size < 64 || s.block_size > kMaxBlock || s.block_size % 64))
     return OSQP_ERR_SETTINGS;
   return OSQP_OK;
@@ -131,6 +134,8 @@ struct osqp_batch {
   int64_t sum_n = 0, sum_m = 0, nnz_a = 0, nnz_p = 0;
   int64_t dense_total = 0, mr_total = 0, dws_stride = 0;
   int dws_slots = 0;
+  int64_t lr_total = 0, lws_stride = 0;   // low-rank blocks / G scratch per workgroup
+  int lws_slots = 0;
   std::vector<int> mrows;
   // host staging of the inputs that change through the parametric API
   std::vector<double> q_raw, l_raw, u_raw;
@@ -257,6 +262,9 @@ void fill_batch_ptrs(Batch<T> &B, osqp_batch *b, Arena &ar, bool alias64) {
   B.dmat = b->dense_total > 0 ? ar.take<T>(b->dense_total) : nullptr;
   B.dws = b->dense_total > 0 ? ar.take<T>((size_t)b->dws_stride * b->dws_slots) : nullptr;
   B.dws_stride = b->dws_stride;
+  B.lmat = b->lr_total > 0 ? ar.take<double>(b->lr_total) : nullptr;
+  B.lws = b->lr_total > 0 ? ar.take<double>((size_t)b->lws_stride * b->lws_slots) : nullptr;
+  B.lws_stride = b->lws_stride;
 }
 
 template <class T>
@@ -477,19 +485,6 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     cost[k] = 2 * probs[k].A.nnz + pfull_nnz[k] + probs[k].n + probs[k].m;
     total += cost[k];
   }
-  for (int k = 0; k < count; ++k) {
-    // a QP the dense path takes stays on a workgroup: its preconditioner
-    // makes the PCG converge in a step or two, and the whole-grid team would
-    // pay a grid barrier per pass
-    const int n = probs[k].n;
-    const bool dense_ok = (s.linsys == OSQP_LINSYS_DENSE && n <= kDenseMaxN) ||
-                          (s.linsys == OSQP_LINSYS_AUTO && n <= kDenseAutoN);
-    const bool big = !dense_ok && cost[k] >= (int64_t)400000 &&
-                     (count == 1 || cost[k] * 64 > total);
-    (big ? b->big_list : b->small_list).push_back(k);
-  }
-  std::stable_sort(b->small_list.begin(), b->small_list.end(),
-                   [&](int a, int c) { return cost[a] > cost[c]; });
   // rows of A with at least two entries (rank-k part of A'RA), all QPs
   for (int k = 0; k < count; ++k) {
     const osqp_problem &p = probs[k];
@@ -498,19 +493,69 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       if (p.A.indptr[i + 1] - p.A.indptr[i] >= 2) b->mrows.push_back(i);
     b->desc[k].mr_cnt = (int)((int64_t)b->mrows.size() - b->desc[k].mr_off);
   }
+  // low-rank eligibility: P diagonal and few multi-entry rows, so that
+  // K = Delta + B'B with B of R <= n/2 rows
+  // (the polishing step takes the same form for its condensed matrix)
+  std::vector<char> lowrank(count, 0);
+  for (int k = 0; k < count; ++k) {
+    const osqp_problem &p = probs[k];
+    bool pdiag = true;
+    for (int i = 0; i < p.n && pdiag; ++i)
+      for (int e = p.P_upper.indptr[i]; e < p.P_upper.indptr[i + 1]; ++e)
+        if (p.P_upper.indices[e] != i) { pdiag = false; break; }
+    const int R = b->desc[k].mr_cnt;
+    const int64_t g = (int64_t)R * ((p.n + 7) & ~7);
+    const bool fits = pdiag && R >= 1 && 2 * R <= p.n && R <= kLowRankMaxR && g <= kLowRankMaxG;
+    b->desc[k].plr = fits ? 1 : 0;
+    lowrank[k] = fits && (s.linsys == OSQP_LINSYS_AUTO || s.linsys == OSQP_LINSYS_LOWRANK);
+  }
+  for (int k = 0; k < count; ++k) {
+    // a QP with an exact preconditioner (dense or low-rank) stays on a
+    // workgroup: its PCG converges in a step or two, and the whole-grid team
+    // would pay a grid barrier per pass
+    const int n = probs[k].n;
+    const bool dense_ok = lowrank[k] ||
+                          (s.linsys == OSQP_LINSYS_DENSE && n <= kDenseMaxN) ||
+                          (s.linsys != OSQP_LINSYS_PCG && n <= kDenseAutoN);
+    const bool big = !dense_ok && cost[k] >= (int64_t)400000 &&
+                     (count == 1 || cost[k] * 64 > total);
+    (big ? b->big_list : b->small_list).push_back(k);
+  }
+  std::stable_sort(b->small_list.begin(), b->small_list.end(),
+                   [&](int a, int c) { return cost[a] > cost[c]; });
   b->mr_total = (int64_t)b->mrows.size();
   // dense preconditioner for workgroup-team QPs up to a size and a memory budget
   {
     const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
     std::vector<int> cand;
+    double lbytes = 0.0;
+    int64_t gmax = 0;
     for (int k : b->small_list) {
       const int n = probs[k].n;
       const bool want = (s.linsys == OSQP_LINSYS_DENSE && n <= kDenseMaxN) ||
-                        (s.linsys == OSQP_LINSYS_AUTO && n <= kDenseAutoN);
-      b->desc[k].dense = 0;
-      b->desc[k].dld = 0;
-      b->desc[k].dense_off = 0;
+                        (s.linsys != OSQP_LINSYS_PCG && n <= kDenseAutoN);
+      QPDesc &d = b->desc[k];
+      d.dense = 0;
+      d.dld = 0;
+      d.dense_off = 0;
+      if (lowrank[k]) {
+        const int R = d.mr_cnt, ldS = (R + 7) & ~7;
+        const LRLayout lo = lr_layout(n, probs[k].m, R, ldS);
+        if (lbytes + 8.0 * (double)lo.total <= kLowRankBudget) {
+          lbytes += 8.0 * (double)lo.total;
+          d.dense = 2;
+          d.dld = ldS;
+          d.dense_off = b->lr_total;
+          b->lr_total += lo.total;
+          gmax = std::max(gmax, (int64_t)R * ((n + 7) & ~7));
+          continue;
+        }
+      }
       if (want) cand.push_back(k);
+    }
+    if (b->lr_total > 0) {
+      b->lws_stride = (gmax + 63) & ~int64_t(63);
+      b->lws_slots = b->grid_wg;
     }
     std::stable_sort(cand.begin(), cand.end(),
                      [&](int a, int c) { return probs[a].n < probs[c].n; });
@@ -675,28 +720,25 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     destroy(b);
     return OSQP_ERR_DEVICE;
   }
-  // polishing workspace: QPs with n <= kPolishMaxN get a dense condensed
-  // system; larger ones are reported as "polish not run"
+  // polishing workspace: QPs with the low-rank condensed form (P diagonal,
+  // few multi-entry rows) and the others with n <= kPolishMaxN (dense
+  // condensed system); larger ones are reported as "polish not run"
   if (s.polish) {
-    int nmax = 0, mmax = 0, rmax = 0;
+    int rmax = 0;
     for (int k = 0; k < count; ++k) {
       const osqp_problem &p = probs[k];
-      if (p.n > kPolishMaxN) continue;
+      if (!b->desc[k].plr && p.n > kPolishMaxN) continue;
       b->polish_list.push_back(k);
-      nmax = std::max(nmax, p.n);
-      mmax = std::max(mmax, p.m);
-      int multi = 0;
-      for (int i = 0; i < p.m; ++i) multi += (p.A.indptr[i + 1] - p.A.indptr[i]) >= 2;
-      rmax = std::max(rmax, multi);
+      rmax = std::max(rmax, b->desc[k].mr_cnt);
     }
     if (!b->polish_list.empty()) {
       std::stable_sort(b->polish_list.begin(), b->polish_list.end(),
                        [&](int a, int c) { return probs[a].n > probs[c].n; });
       b->polish_rmax = rmax;
-      const long long ldm = (nmax + 7) & ~7;
-      b->pws_stride = (long long)nmax * ldm + (long long)((nmax + 63) / 64) * 64 * 64 +
-                      (long long)rmax * nmax + 3LL * nmax + 5LL * mmax + 64;
-      b->pws_stride = (b->pws_stride + 7) & ~7LL;   // 64-byte slot bases (16-byte loads)
+      int64_t stride = 0;
+      for (int k : b->polish_list)
+        stride = std::max(stride, polish_ws_doubles(probs[k].n, probs[k].m, rmax, b->desc[k].plr != 0));
+      b->pws_stride = (stride + 7) & ~int64_t(7);   // 64-byte slot bases (16-byte loads)
       b->polish_slots = std::max(1, std::min((int)b->polish_list.size(),
                                              prop.multiProcessorCount));
       if (hipMalloc(&b->d_pws, sizeof(double) * b->pws_stride * b->polish_slots) != hipSuccess ||
@@ -726,6 +768,10 @@ void fill_info(const osqp_batch *b, int k, osqp_info *info) {
   info->pcg_iter = S.pcg_iter;
   info->rho_updates = S.rho_updates;
   info->polish_status = S.polish_status;
+  {
+    const int dk = b->desc[k].dense;
+    info->linsys = dk == 1 ? OSQP_LINSYS_DENSE : (dk == 2 ? OSQP_LINSYS_LOWRANK : OSQP_LINSYS_PCG);
+  }
   info->obj_val = S.obj;
   info->prim_res = S.prim_res;
   info->dual_res = S.dual_res;
@@ -1023,7 +1069,7 @@ osqp_int osqp_batch_get_factor(const osqp_batch *b, osqp_int i, osqp_float *L_ou
   if (!b || !L_out) return OSQP_ERR_NOT_SETUP;
   if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
   const QPDesc &d = b->desc[i];
-  if (!d.dense) return OSQP_ERR_NOT_SETUP;
+  if (d.dense != 1) return OSQP_ERR_NOT_SETUP;
   QPState st;
   const QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
   if (hipMemcpy(&st, dst + i, sizeof(QPState), hipMemcpyDeviceToHost) != hipSuccess)

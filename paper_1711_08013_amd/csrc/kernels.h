@@ -48,17 +48,28 @@ __global__ void __launch_bounds__(kMaxBlock) rescale_vectors_wg_kernel(Batch<T> 
   rescale_vectors<T>(tm, v);
 }
 
+// LDS of the exact preconditioners: the dense path works in T, the low-rank
+// path in double; a QP uses one of them, so they share storage.
+template <class T>
+struct SolveLDS {
+  union {
+    DenseLDS<T> t;
+    DenseLDS<double> d;
+  };
+};
+
 template <class T>
 __global__ void __launch_bounds__(kMaxBlock) solve_wg_kernel(Batch<T> b, const int *list,
                                                              int nlist, int slot) {
   __shared__ double red[(kMaxBlock / kWave) * kRedSlots];
-  __shared__ DenseLDS<T> dl;
+  __shared__ SolveLDS<T> dl;
   WGTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   T *dB = b.dws ? b.dws + (size_t)blockIdx.x * (size_t)b.dws_stride : nullptr;
+  double *G = b.lws ? b.lws + (size_t)blockIdx.x * (size_t)b.lws_stride : nullptr;
   __shared__ int slot_val;
   wg_queue(b.counter + slot, nlist, slot_val, [&](int qi) __attribute__((always_inline)) {
     QPView<T> v(b, list[qi]);
-    solve_qp<T>(tm, v, b.set, &dl, dB, dB != nullptr);
+    solve_qp<T>(tm, v, b.set, &dl.t, dB, dB != nullptr, &dl.d, G, G != nullptr);
   });
 }
 
@@ -78,7 +89,7 @@ __global__ void __launch_bounds__(kPolishBlock) polish_wg_kernel(Batch<T> b, con
     const int k = list[qi];
     if (b.st[k].status != 1) return;
     QPView<T> v(b, k);
-    polish_qp<T>(tm, dl, v, b.set, mine, rmax);
+    polish_qp<T>(tm, dl, v, b.set, mine, rmax, b.desc[k].plr != 0);
   });
 }
 

@@ -5,14 +5,17 @@
 //     [ P + dI   A_a' ] [x  ]   [ -q  ]
 //     [ A_a     -dI   ] [y_a] = [ b_a ],  b_a = l_L, u_U
 // is solved through its condensed SPD form
-//     (P + dI + A_a'A_a / d) x = -q + A_a' b_a / d,   y_a = (A_a x - b_a) / d,
-// formed densely (single-entry active rows only add to the diagonal, the
-// others go through a rank-k update) and factored once by a dense Cholesky.
-// Then the fixed number of iterative-refinement passes of eq.
-// iterative_refinement against the unregularised matrix (eq. kkt_polish),
-// each a pair of triangular solves.  The polished point is accepted when its
-// unscaled residuals do not exceed the ADMM ones and the active duals keep
-// their signs (reading); otherwise the ADMM solution stays.
+//     M x = -q + A_a' b_a / d,   M = P + dI + A_a'A_a / d,   y_a = (A_a x - b_a) / d.
+// Single-entry active rows only add to the diagonal of M; the active rows
+// with several entries form B = A_m / sqrt(d).  M is either formed densely
+// and factored by a dense Cholesky, or -- when P is diagonal and the
+// multi-entry rows are few (flag plr of the QP) -- kept as Delta + B'B and
+// solved by the Woodbury identity with the small capacitance matrix
+// S = I + B Delta^-1 B'.  Then the fixed number of iterative-refinement
+// passes of eq. iterative_refinement against the unregularised matrix (eq.
+// kkt_polish), each one more solve with M.  The polished point is accepted
+// when its unscaled residuals do not exceed the ADMM ones and the active
+// duals keep their signs (reading); otherwise the ADMM solution stays.
 #pragma once
 
 #include "dense.h"
@@ -20,30 +23,54 @@
 
 namespace osqpmi {
 
-struct PolishWS {
-  double *base;
-  long long stride;   // doubles per workgroup slot
-  int nmax, rmax, mmax;
-};
+// Workspace (doubles) of one polishing slot.  Dense: M (n x ldm), the
+// inverses of its 64 x 64 diagonal blocks, B (rmax x n).  Low-rank: Delta^-1,
+// u, S (rmax x ldS), its block inverses, w compact, w by row, G (rmax x ldg).
+// Then the vectors of both variants.
+__host__ __device__ inline int64_t polish_ws_doubles(int n, int m, int rmax, bool lowrank) {
+  const int64_t n8 = (n + 7) & ~7, m8 = (m + 7) & ~7, r8 = (rmax + 7) & ~7;
+  int64_t head;
+  if (lowrank)
+    head = 2 * n8 + (int64_t)rmax * r8 + (int64_t)((rmax + 63) / 64) * 4096 + r8 + m8 +
+           (int64_t)rmax * n8;
+  else
+    head = n * n8 + (int64_t)((n + 63) / 64) * 4096 + (int64_t)rmax * n;
+  return ((head + 7) & ~int64_t(7)) + 3 * n8 + 5 * m8 + 64;
+}
 
 template <class T>
 __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s, const QPView<T> &v,
-                          const DevSettings &set, double *ws, int rmax) {
+                                          const DevSettings &set, double *ws, int rmax, bool lowrank) {
   const int n = v.n, m = v.m;
-  const double delta = set.delta, dinv = 1.0 / delta;
+  const double delta = set.delta, dinv_d = 1.0 / delta, rs = sqrt(dinv_d);
   const double c = v.st->c, cinv = 1.0 / c;
   const unsigned long long t0 = wall_clock64();
-  const int ldm = (n + 7) & ~7;                    // row stride of M (16-byte rows)
-  const int nblk = (n + kSB - 1) / kSB;
-  double *M = ws;                                  // n x ldm
-  double *Minv = M + (size_t)n * ldm;              // nblk inverted 64 x 64 diagonal blocks
-  double *B = Minv + (size_t)nblk * kSB * kSB;     // rmax x n
-  double *act = B + (size_t)rmax * n;              // m: -1, 0, +1
-  double *bact = act + m;                          // m
-  double *tx = bact + m, *ty = tx + n;             // n, m
-  double *rx = ty + m, *ry = rx + n;               // n, m
-  double *g = ry + m;                              // n
-  int *multi = reinterpret_cast<int *>(g + n);     // m
+  const int n8 = (n + 7) & ~7, m8 = (m + 7) & ~7, r8 = (rmax + 7) & ~7;
+  const int nblk = (n + kSB - 1) / kSB, rblk = (rmax + kSB - 1) / kSB;
+  // matrix part
+  double *M = ws, *Minv = nullptr, *B = nullptr;                 // dense
+  double *Dl = ws, *u = nullptr, *S = nullptr, *Sinv = nullptr;  // low-rank
+  double *wc = nullptr, *wr = nullptr, *G = nullptr;
+  int64_t head;
+  if (lowrank) {
+    u = Dl + n8;
+    S = u + n8;
+    Sinv = S + (size_t)rmax * r8;
+    wc = Sinv + (size_t)rblk * 4096;
+    wr = wc + r8;
+    G = wr + m8;
+    head = (G - ws) + (int64_t)rmax * n8;
+  } else {
+    Minv = M + (size_t)n * n8;
+    B = Minv + (size_t)nblk * 4096;
+    head = (B - ws) + (int64_t)rmax * n;
+  }
+  double *act = ws + ((head + 7) & ~int64_t(7));   // m: -1, 0, +1
+  double *bact = act + m8;                         // m
+  double *tx = bact + m8, *ty = tx + n8;           // n, m
+  double *rx = ty + m8, *ry = rx + n8;             // n, m
+  double *g = ry + m8;                             // n
+  int *multi = reinterpret_cast<int *>(g + n8);    // m
   __shared__ int R_sh;
 
   for (int i = tm.tid; i < m; i += tm.nt) {
@@ -59,34 +86,90 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] >= 2) multi[R++] = i;
     R_sh = R;
   }
-  for (size_t e = tm.tid; e < (size_t)n * ldm; e += tm.nt) M[e] = 0.0;
   tm.sync();
   const int R = min(R_sh, rmax);
-  for (size_t e = tm.tid; e < (size_t)R * n; e += tm.nt) B[e] = 0.0;
-  tm.sync();
-  // P + d I, plus the single-entry active rows on the diagonal
-  for (int j = tm.tid; j < n; j += tm.nt) {
-    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) M[(size_t)j * ldm + v.pci[k]] = v.p64[k];
-    double dsum = delta;
-    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
-      const int i = v.atci[k];
-      if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] == 1) dsum += v.at64[k] * v.at64[k] * dinv;
+  bool ok_fact;
+  if (lowrank) {
+    // Delta = diag(P) + d + single-entry active rows a^2 / d;  G = B Delta^-1/2
+    for (int j = tm.tid; j < n; j += tm.nt) {
+      double a = delta;
+      for (int k = v.prp[j]; k < v.prp[j + 1]; ++k)
+        if (v.pci[k] == j) a += v.p64[k];
+      for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
+        const int i = v.atci[k];
+        if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] == 1) a += v.at64[k] * v.at64[k] * dinv_d;
+      }
+      Dl[j] = 1.0 / a;
     }
-    M[(size_t)j * ldm + j] += dsum;
+    for (size_t e = tm.tid; e < (size_t)R * n8; e += tm.nt) G[e] = 0.0;
+    for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;
+    tm.sync();
+    for (int r = tm.tid; r < R; r += tm.nt) {
+      const int i = multi[r];
+      for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) {
+        const int j = v.aci[k];
+        G[(size_t)r * n8 + j] = v.a64[k] * rs * sqrt(Dl[j]);
+      }
+    }
+    tm.sync();
+    dense_gram_lower(tm, s, G, n8, R, n, S, r8);
+    for (int r = tm.tid; r < R; r += tm.nt) S[(size_t)r * r8 + r] += 1.0;
+    tm.sync();
+    ok_fact = dense_cholesky<double>(tm, s, S, r8, R) && R_sh <= rmax;
+    if (ok_fact) dense_invert_diag<double>(tm, s, S, r8, R, Sinv);
+  } else {
+    for (size_t e = tm.tid; e < (size_t)n * n8; e += tm.nt) M[e] = 0.0;
+    for (size_t e = tm.tid; e < (size_t)R * n; e += tm.nt) B[e] = 0.0;
+    tm.sync();
+    // P + d I, plus the single-entry active rows on the diagonal
+    for (int j = tm.tid; j < n; j += tm.nt) {
+      for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) M[(size_t)j * n8 + v.pci[k]] = v.p64[k];
+      double dsum = delta;
+      for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
+        const int i = v.atci[k];
+        if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] == 1) dsum += v.at64[k] * v.at64[k] * dinv_d;
+      }
+      M[(size_t)j * n8 + j] += dsum;
+    }
+    for (int r = tm.tid; r < R; r += tm.nt) {
+      const int i = multi[r];
+      for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) B[(size_t)r * n + v.aci[k]] = v.a64[k];
+    }
+    tm.sync();
+    dense_syrk_tn<double>(tm, s, M, n8, B, n, R, n, dinv_d);
+    ok_fact = dense_cholesky<double>(tm, s, M, n8, n) && R_sh <= rmax;
+    if (ok_fact) dense_invert_diag<double>(tm, s, M, n8, n, Minv);
   }
-  for (int r = tm.tid; r < R; r += tm.nt) {
-    const int i = multi[r];
-    for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) B[(size_t)r * n + v.aci[k]] = v.a64[k];
-  }
-  tm.sync();
-  dense_syrk_tn<double>(tm, s, M, ldm, B, n, R, n, dinv);
-  const bool ok_fact = dense_cholesky<double>(tm, s, M, ldm, n) && R_sh <= rmax;
-  if (ok_fact) dense_invert_diag<double>(tm, s, M, ldm, n, Minv);
   if (!ok_fact) {
     if (tm.tid == 0) v.st->polish_status = -1;
     tm.sync();
     return;
   }
+  // g <- M^-1 g (in place)
+  auto msolve = [&]() __attribute__((always_inline)) {
+    if (lowrank) {
+      for (int j = tm.tid; j < n; j += tm.nt) u[j] = Dl[j] * g[j];
+      tm.sync();
+      for (int r = tm.tid; r < R; r += tm.nt) {
+        const int i = multi[r];
+        double a = 0.0;
+        for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * u[v.aci[k]];
+        wc[r] = rs * a;
+      }
+      tm.sync();
+      dense_solve_llt<double>(tm, s, S, r8, R, Sinv, wc);
+      for (int r = tm.tid; r < R; r += tm.nt) wr[multi[r]] = rs * wc[r];
+      tm.sync();
+      for (int j = tm.tid; j < n; j += tm.nt) {
+        double a = 0.0;
+        for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) a += v.at64[k] * wr[v.atci[k]];
+        g[j] = u[j] - Dl[j] * a;
+      }
+      tm.sync();
+    } else {
+      dense_solve_llt<double>(tm, s, M, n8, n, Minv, g);
+    }
+  };
   // first solve: rhs = -q + A_a' b_a / d
   for (int j = tm.tid; j < n; j += tm.nt) {
     double a = 0.0;
@@ -94,17 +177,17 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       const int i = v.atci[k];
       a += v.at64[k] * bact[i];     // bact is 0 on inactive rows
     }
-    g[j] = -v.q64[j] + a * dinv;
+    g[j] = -v.q64[j] + a * dinv_d;
   }
   tm.sync();
-  dense_solve_llt<double>(tm, s, M, ldm, n, Minv, g);
+  msolve();
   for (int j = tm.tid; j < n; j += tm.nt) tx[j] = g[j];
   tm.sync();
   for (int i = tm.tid; i < m; i += tm.nt) {
     double a = 0.0;
     if (act[i] != 0.0)
       for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * tx[v.aci[k]];
-    ty[i] = act[i] != 0.0 ? (a - bact[i]) * dinv : 0.0;
+    ty[i] = act[i] != 0.0 ? (a - bact[i]) * dinv_d : 0.0;
   }
   tm.sync();
   // iterative refinement: t += (K + dK)^-1 (g - K t), K without d
@@ -125,15 +208,15 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     for (int j = tm.tid; j < n; j += tm.nt) {
       double a = 0.0;
       for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) a += v.at64[k] * ry[v.atci[k]];
-      g[j] = rx[j] + a * dinv;
+      g[j] = rx[j] + a * dinv_d;
     }
     tm.sync();
-    dense_solve_llt<double>(tm, s, M, ldm, n, Minv, g);
+    msolve();
     for (int i = tm.tid; i < m; i += tm.nt) {
       double a = 0.0;
       if (act[i] != 0.0)
         for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * g[v.aci[k]];
-      if (act[i] != 0.0) ty[i] += (a - ry[i]) * dinv;
+      if (act[i] != 0.0) ty[i] += (a - ry[i]) * dinv_d;
     }
     tm.sync();
     for (int j = tm.tid; j < n; j += tm.nt) tx[j] += g[j];
@@ -185,16 +268,16 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     }
   }
   if (tm.tid == 0) {
-    QPState &S = *v.st;
-    S.polish_status = accept ? 1 : -1;
+    QPState &St = *v.st;
+    St.polish_status = accept ? 1 : -1;
     if (accept) {
-      S.obj = cinv * red[0];
-      S.prim_res = prim;
-      S.dual_res = dual;
-      S.eps_prim = set.eps_abs + set.eps_rel * fmax(red[2], red[3]);
-      S.eps_dual = set.eps_abs + set.eps_rel * cinv * fmax(red[5], fmax(red[6], red[7]));
+      St.obj = cinv * red[0];
+      St.prim_res = prim;
+      St.dual_res = dual;
+      St.eps_prim = set.eps_abs + set.eps_rel * fmax(red[2], red[3]);
+      St.eps_dual = set.eps_abs + set.eps_rel * cinv * fmax(red[5], fmax(red[6], red[7]));
     }
-    S.polish_ms = double(wall_clock64() - t0) * set.wall_tick_s * 1e3;
+    St.polish_ms = double(wall_clock64() - t0) * set.wall_tick_s * 1e3;
   }
   tm.sync();
 }

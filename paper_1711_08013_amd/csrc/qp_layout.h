@@ -16,13 +16,34 @@ struct QPDesc {
   int64_t a_rp, at_rp, p_rp; // row-pointer array offsets (m+1, n+1, n+1 entries)
   int64_t a_nz, at_nz, p_nz; // entry offsets
   int lm, ln;                // lanes per row for passes over A rows / over P+A' rows
-  int dense;                 // 1: dense factor of P + sigma I + A'RA as PCG preconditioner
-  int dld;                   // leading dimension of that factor
-  int64_t dense_off;         // offset of the factor in the dense arena
+  int dense;                 // exact PCG preconditioner of P + sigma I + A'RA:
+                             // 0 none (Jacobi), 1 dense Cholesky factor,
+                             // 2 diagonal plus low rank (P diagonal; Woodbury)
+  int dld;                   // leading dimension of the dense factor / of S
+  int64_t dense_off;         // offset in the dense arena (1) or low-rank arena (2)
   int64_t mr_off;            // offset of the list of A rows with >= 2 entries
   int mr_cnt;                // length of that list
-  int pad;
+  int plr;                   // 1: polish through the low-rank (Woodbury) condensed solve
 };
+
+// Offsets (doubles) inside one QP's low-rank block: Delta^-1 at 0, then u
+// (n), the capacitance matrix S (R x ldS, lower), the inverses of its 64 x 64
+// diagonal blocks, w compact (R) and w scattered by row of A (m).  Every
+// part starts on a multiple of 8 doubles.
+struct LRLayout {
+  int64_t u, S, Sinv, wc, wr, total;
+};
+__host__ __device__ inline LRLayout lr_layout(int n, int m, int R, int ldS) {
+  const int64_t n8 = (n + 7) & ~7, m8 = (m + 7) & ~7, R8 = (R + 7) & ~7;
+  LRLayout L;
+  L.u = n8;
+  L.S = L.u + n8;
+  L.Sinv = L.S + (int64_t)R * ldS;
+  L.wc = L.Sinv + (int64_t)((R + 63) / 64) * 64 * 64;
+  L.wr = L.wc + R8;
+  L.total = L.wr + m8;
+  return L;
+}
 
 // Per-QP mutable state (device).
 struct QPState {
@@ -79,6 +100,11 @@ struct Batch {
   T *dmat;
   T *dws;
   long long dws_stride;
+  // low-rank path (FP64): per-QP blocks [Delta^-1 | u | S | S-block
+  // inverses | w (compact) | w (by row)] and per-workgroup G scratch
+  double *lmat;
+  double *lws;
+  long long lws_stride;
   const int *mrows;
   DevSettings set;
 };

@@ -36,6 +36,7 @@ struct QPView {
   QPState *st;
   T *L;              // dense factor (row-major, lower), when dense
   T *Linv;           // inverses of its 64 x 64 diagonal blocks (after L)
+  double *lr;        // low-rank block (lr_layout), when dense == 2
   int ld, dense, mr_cnt;
   const int *mrows;
 
@@ -63,8 +64,9 @@ struct QPView {
     xo = b.xo + ds.xo; yo = b.yo + ds.yo; zo = b.zo + ds.yo;
     st = b.st + k;
     dense = ds.dense; ld = ds.dld; mr_cnt = ds.mr_cnt;
-    L = ds.dense ? b.dmat + ds.dense_off : nullptr;
-    Linv = ds.dense ? L + (size_t)ds.n * ds.dld : nullptr;
+    L = ds.dense == 1 ? b.dmat + ds.dense_off : nullptr;
+    Linv = ds.dense == 1 ? L + (size_t)ds.n * ds.dld : nullptr;
+    lr = ds.dense == 2 ? b.lmat + ds.dense_off : nullptr;
     mrows = b.mrows + ds.mr_off;
   }
 };
@@ -298,12 +300,101 @@ __device__ __forceinline__ void precondition_dense(const WGTeam &tm, const QPVie
 }
 
 // ------------------------------------------------------------------------
+// Diagonal-plus-low-rank path (P diagonal).  With the rows of A split into
+// single-entry rows and the R multi-entry rows A_m,
+//     K = P + sigma I + A'RA = Delta + B'B,   B = R_m^1/2 A_m  (R x n),
+// Delta = diag(P) + sigma + sum over single-entry rows of rho_i a_ij^2.
+// The Woodbury identity gives K^-1 r = u - Delta^-1 B' S^-1 B u with
+// u = Delta^-1 r and the R x R capacitance matrix S = I + B Delta^-1 B',
+// factored once per rho-bar in FP64 (S = G G' + I, G = B Delta^-1/2 formed
+// densely in the workgroup's scratch).  This is the same reduced system the
+// dense factor solves, at O(R^2 n) set-up and O(nnz(A_m)) per apply.
+// ------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const QPView<T> &v,
+                                                        DenseLDS<double> &s, double *G,
+                                                        double sigma, double rho_bar) {
+  const int n = v.n, m = v.m, R = v.mr_cnt, ldS = v.ld, ldg = (n + 7) & ~7;
+  const LRLayout lo = lr_layout(n, m, R, ldS);
+  double *dinv = v.lr, *S = v.lr + lo.S, *Sinv = v.lr + lo.Sinv, *wr = v.lr + lo.wr;
+  auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
+  for (int j = tm.tid; j < n; j += tm.nt) {
+    double a = sigma;
+    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k)
+      if (v.pci[k] == j) a += v.p64[k];
+    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
+      const int i = v.atci[k];
+      if (v.arp[i + 1] - v.arp[i] == 1) {
+        const double e = v.at64[k];
+        a += rho_i(i) * e * e;
+      }
+    }
+    dinv[j] = 1.0 / a;
+  }
+  for (size_t e = tm.tid; e < (size_t)R * ldg; e += tm.nt) G[e] = 0.0;
+  for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;   // single-entry rows stay 0
+  tm.sync();
+  const Rows rm(tm, v.lm);
+  for (int r = rm.g; r < R; r += rm.ng) {
+    const int i = v.mrows[r];
+    const double sr = sqrt(rho_i(i));
+    for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L) {
+      const int j = v.aci[k];
+      G[(size_t)r * ldg + j] = sr * v.a64[k] * sqrt(dinv[j]);
+    }
+  }
+  tm.sync();
+  dense_gram_lower(tm, s, G, ldg, R, n, S, ldS);
+  for (int r = tm.tid; r < R; r += tm.nt) S[(size_t)r * ldS + r] += 1.0;
+  tm.sync();
+  const bool ok = dense_cholesky<double>(tm, s, S, ldS, R);
+  if (ok) dense_invert_diag<double>(tm, s, S, ldS, R, Sinv);
+  return ok;
+}
+
+// d = K^-1 r by the Woodbury identity (FP64 inside, d rounded to T).
+template <class T>
+__device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPView<T> &v,
+                                                     DenseLDS<double> &s, double rho_bar) {
+  const int n = v.n, m = v.m, R = v.mr_cnt, ldS = v.ld;
+  const LRLayout lo = lr_layout(n, m, R, ldS);
+  const double *dinv = v.lr, *S = v.lr + lo.S, *Sinv = v.lr + lo.Sinv;
+  double *u = v.lr + lo.u, *wc = v.lr + lo.wc, *wr = v.lr + lo.wr;
+  auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
+  tm.sync();
+  for (int j = tm.tid; j < n; j += tm.nt) u[j] = dinv[j] * double(v.r[j]);
+  tm.sync();
+  // wc = B u over the multi-entry rows
+  const Rows rm(tm, v.lm);
+  for (int r = rm.g; r < R; r += rm.ng) {
+    const int i = v.mrows[r];
+    const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, u), rm.L);
+    if (rm.lane == 0) wc[r] = sqrt(rho_i(i)) * a;
+  }
+  tm.sync();
+  dense_solve_llt<double>(tm, s, S, ldS, R, Sinv, wc);
+  for (int r = tm.tid; r < R; r += tm.nt) {
+    const int i = v.mrows[r];
+    wr[i] = sqrt(rho_i(i)) * wc[r];
+  }
+  tm.sync();
+  // d = u - Delta^-1 B' w  (B' w through the rows of A'; zero on single-entry rows)
+  const Rows rn(tm, v.ln);
+  for (int j = rn.g; j < n; j += rn.ng) {
+    const double a = group_sum(row_partial<double>(v.atrp, v.atci, v.at64, j, rn.lane, rn.L, wr), rn.L);
+    if (rn.lane == 0) v.d[j] = T(u[j] - dinv[j] * a);
+  }
+  tm.sync();
+}
+
+// ------------------------------------------------------------------------
 // One full solve of one QP (Algorithm 1 with the reduced-system PCG of
 // Section 3.1), then the FP64 checks, statuses and unscaled outputs.
 // ------------------------------------------------------------------------
 template <class T, class Team>
 __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &set,
-                         DenseLDS<T> *dl = nullptr, T *dB = nullptr, bool dense_ok = false) {
+                         DenseLDS<T> *dl = nullptr, T *dB = nullptr, bool dense_ok = false,
+                         DenseLDS<double> *dl64 = nullptr, double *G = nullptr, bool lr_ok = false) {
   const int n = v.n, m = v.m;
   const T sigma = T(set.sigma);
   const double c = v.st->c, cinv = 1.0 / c;
@@ -321,14 +412,30 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   };
 
   set_rho_and_precond(tm, v, rho_bar, set.sigma);
-  // dense preconditioner: reuse the stored factor while rho-bar is unchanged
+  // exact preconditioner of K (dense factor, or the low-rank Woodbury form):
+  // the stored factor is reused while rho-bar is unchanged
+  const int pre_kind = (v.dense == 1 && dense_ok) ? 1 : ((v.dense == 2 && lr_ok) ? 2 : 0);
+  auto refactor = [&]() __attribute__((always_inline)) -> bool {
+    if constexpr (std::is_same<Team, WGTeam>::value) {
+      if (pre_kind == 1) return form_and_factor<T>(tm, v, *dl, dB, set.sigma);
+      return lowrank_form_and_factor<T>(tm, v, *dl64, G, set.sigma, rho_bar);
+    } else {
+      return false;
+    }
+  };
+  auto apply_pre = [&]() __attribute__((always_inline)) {
+    if constexpr (std::is_same<Team, WGTeam>::value) {
+      if (pre_kind == 1) precondition_dense(tm, v, *dl);
+      else precondition_lowrank(tm, v, *dl64, rho_bar);
+    }
+  };
   bool use_dense = false;
   if constexpr (std::is_same<Team, WGTeam>::value) {
-    if (v.dense && dense_ok) {
+    if (pre_kind != 0) {
       use_dense = true;
       if (v.st->factor_rho != rho_bar) {
         ph = wall_clock64();
-        use_dense = form_and_factor<T>(tm, v, *dl, dB, set.sigma);
+        use_dense = refactor();
         if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
         tm.sync();
         lap(c_factor);
@@ -411,7 +518,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         tm.template reduce<0, 1>(red + 1);
         dense_skip = bnorm >= 0.0 && red[1] <= pcg_tol(bnorm);
         if (!dense_skip) {
-          precondition_dense(tm, v, *dl);
+          apply_pre();
           for (int j = tm.tid; j < n; j += tm.nt) {
             const T dj = v.d[j];
             v.p[j] = dj;
@@ -475,7 +582,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
           tm.template reduce<0, 1>(red + 1);
           converged = red[1] <= tol;
           if (!converged) {
-            precondition_dense(tm, v, *dl);
+            apply_pre();
             for (int j = tm.tid; j < n; j += tm.nt) red[0] += double(v.r[j] * v.d[j]);
             tm.template reduce<1, 0>(red);
           }
@@ -643,8 +750,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         ++rho_updates;
         set_rho_and_precond(tm, v, rho_bar, set.sigma);
         if constexpr (std::is_same<Team, WGTeam>::value) {
-          if (v.dense && dense_ok) {
-            use_dense = form_and_factor<T>(tm, v, *dl, dB, set.sigma);
+          if (pre_kind != 0) {
+            use_dense = refactor();
             if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
             tm.sync();
             lap(c_factor);
