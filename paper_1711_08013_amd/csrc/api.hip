@@ -432,7 +432,15 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       wall_khz <= 0)
     wall_khz = 100000;
   b->wall_tick_s = 1.0 / (1e3 * wall_khz);
-  b->block = s.block_size ? s.block_size : 256;
+  // workgroup size: the passes of one QP are latency-bound per wave, so QPs
+  // with long passes get 512 threads (one workgroup per CU), small ones 256
+  // (two per CU, more QPs in flight)
+  {
+    int64_t big_nnz = 0;
+    for (int k = 0; k < count; ++k)
+      big_nnz = std::max<int64_t>(big_nnz, (int64_t)probs[k].A.nnz + 2 * probs[k].P_upper.nnz);
+    b->block = s.block_size ? s.block_size : (big_nnz >= 20000 ? 512 : 256);
+  }
   int per_cu = 1;
   if (b->fp64)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<double>, b->block, 0);

@@ -35,6 +35,13 @@ struct DenseLDS {
   int flag;
 };
 
+// Doubles of LDS a workgroup may use to stage a gathered vector; the stage
+// overlays the factorisation tiles of DenseLDS<double> (never live at the
+// same time) and stays clear of its ys and flag, which the triangular solve
+// uses while a stage is live.
+constexpr int kStage = 8192;
+static_assert(kStage * sizeof(double) <= 2 * 64 * 65 * sizeof(double), "stage overlaps ys");
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 

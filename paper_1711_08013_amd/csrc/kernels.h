@@ -55,6 +55,7 @@ struct SolveLDS {
   union {
     DenseLDS<T> t;
     DenseLDS<double> d;
+    double stage[kStage];   // gathered vectors of the sparse passes
   };
 };
 
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(kMaxBlock) solve_wg_kernel(Batch<T> b, const i
   __shared__ int slot_val;
   wg_queue(b.counter + slot, nlist, slot_val, [&](int qi) __attribute__((always_inline)) {
     QPView<T> v(b, list[qi]);
-    solve_qp<T>(tm, v, b.set, &dl.t, dB, dB != nullptr, &dl.d, G, G != nullptr);
+    solve_qp<T>(tm, v, b.set, &dl.t, dB, dB != nullptr, &dl.d, G, G != nullptr, dl.stage);
   });
 }
 

@@ -80,33 +80,97 @@ struct Rows {
   }
 };
 
-// Partial dot of CSR row r with x over the lanes of a group (not reduced).
-// Four entries per lane are gathered per round so that their loads are in
-// flight together.
+// Partial dot over the lanes of a group of sum_k v[k] x[ci[k]], k in [b, e)
+// (not reduced).  Each round gathers eight entries per lane with predicated
+// loads, all in flight together: the passes are bound by memory latency per
+// wave, not by arithmetic, and a row needs ceil(len / 8L) rounds.
 template <class A, class V, class X>
-__device__ __forceinline__ A row_partial(const int *rp, const int *ci, const V *v, int r,
-                                         int lane, int L, const X *x) {
+__device__ __forceinline__ A seg_partial(const int *ci, const V *v, int b, int e, int lane, int L,
+                                         const X *x) {
   A s0 = A(0), s1 = A(0), s2 = A(0), s3 = A(0);
-  const int e = rp[r + 1];
-  int k = rp[r] + lane;
-  for (; k + 3 * L < e; k += 4 * L) {
-    const int c0 = ci[k], c1 = ci[k + L], c2 = ci[k + 2 * L], c3 = ci[k + 3 * L];
-    const A a0 = A(v[k]), a1 = A(v[k + L]), a2 = A(v[k + 2 * L]), a3 = A(v[k + 3 * L]);
-    s0 += a0 * A(x[c0]); s1 += a1 * A(x[c1]); s2 += a2 * A(x[c2]); s3 += a3 * A(x[c3]);
+  for (int k = b + lane; k < e; k += 8 * L) {
+    int c[8];
+    A a[8];
+    // positions past the row's end re-read its last entry (always in
+    // range, since k < e) and contribute zero: the loads stay unconditional,
+    // so none of them waits for another
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int kk = min(k + u * L, e - 1);
+      c[u] = ci[kk];
+      a[u] = A(v[kk]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k + u * L >= e) a[u] = A(0);
+    s0 += a[0] * A(x[c[0]]); s1 += a[1] * A(x[c[1]]);
+    s2 += a[2] * A(x[c[2]]); s3 += a[3] * A(x[c[3]]);
+    s0 += a[4] * A(x[c[4]]); s1 += a[5] * A(x[c[5]]);
+    s2 += a[6] * A(x[c[6]]); s3 += a[7] * A(x[c[7]]);
   }
-  for (; k < e; k += L) s0 += A(v[k]) * A(x[ci[k]]);
   return (s0 + s1) + (s2 + s3);
 }
 
+// The same for CSR row r.
+template <class A, class V, class X>
+__device__ __forceinline__ A row_partial(const int *rp, const int *ci, const V *v, int r,
+                                         int lane, int L, const X *x) {
+  return seg_partial<A>(ci, v, rp[r], rp[r + 1], lane, L, x);
+}
+
+// Rows j = g, g + ng, ... < cnt of one CSR (rp) or of two with the same row
+// count (rp, rp2): f(j, b, e[, b2, e2]) gets the row bounds, which were
+// loaded one step ahead so that their latency hides behind the previous row.
+template <class F>
+__device__ __forceinline__ void rows_ahead(const int *rp, int g, int ng, int cnt, F &&f) {
+  int j = g;
+  int b = j < cnt ? rp[j] : 0, e = j < cnt ? rp[j + 1] : 0;
+  while (j < cnt) {
+    const int jn = j + ng;
+    const int bn = jn < cnt ? rp[jn] : 0, en = jn < cnt ? rp[jn + 1] : 0;
+    f(j, b, e);
+    j = jn; b = bn; e = en;
+  }
+}
+template <class F>
+__device__ __forceinline__ void rows_ahead2(const int *rp, const int *rp2, int g, int ng, int cnt,
+                                            F &&f) {
+  int j = g;
+  int b = 0, e = 0, b2 = 0, e2 = 0;
+  if (j < cnt) { b = rp[j]; e = rp[j + 1]; b2 = rp2[j]; e2 = rp2[j + 1]; }
+  while (j < cnt) {
+    const int jn = j + ng;
+    int bn = 0, en = 0, bn2 = 0, en2 = 0;
+    if (jn < cnt) { bn = rp[jn]; en = rp[jn + 1]; bn2 = rp2[jn]; en2 = rp2[jn + 1]; }
+    f(j, b, e, b2, e2);
+    j = jn; b = bn; e = en; b2 = bn2; e2 = en2;
+  }
+}
+
 // A pass over the rows of A: rows with at most one entry take one lane each,
-// the rows with several entries (the list mrows) a group of rm.L lanes.
-// body(i, lane, L) reduces over its L lanes; lane 0 holds the result.
+// the rows with several entries (the list mrows) a group of rm.L lanes, the
+// next row's index and bounds loaded ahead.  body(i, b, e, lane, L) reduces
+// over its L lanes; lane 0 holds the result.
 template <class T, class Team, class Body>
 __device__ __forceinline__ void for_a_rows(const Team &tm, const QPView<T> &v, const Rows &rm,
                                            Body &&body) {
-  for (int i = tm.tid; i < v.m; i += tm.nt)
-    if (v.arp[i + 1] - v.arp[i] <= 1) body(i, 0, 1);
-  for (int r = rm.g; r < v.mr_cnt; r += rm.ng) body(v.mrows[r], rm.lane, rm.L);
+  for (int i = tm.tid; i < v.m; i += tm.nt) {
+    const int b = v.arp[i], e = v.arp[i + 1];
+    if (e - b <= 1) body(i, b, e, 0, 1);
+  }
+  const int cnt = v.mr_cnt, ng = rm.ng;
+  int r = rm.g;
+  int i = r < cnt ? v.mrows[r] : 0;
+  int b = r < cnt ? v.arp[i] : 0, e = r < cnt ? v.arp[i + 1] : 0;
+  int r2 = r + ng;
+  int i2 = r2 < cnt ? v.mrows[r2] : 0;
+  while (r < cnt) {
+    const int r3 = r2 + ng;
+    const int i3 = r3 < cnt ? v.mrows[r3] : 0;
+    const int b2 = r2 < cnt ? v.arp[i2] : 0, e2 = r2 < cnt ? v.arp[i2 + 1] : 0;
+    body(i, b, e, rm.lane, rm.L);
+    r = r2; i = i2; b = b2; e = e2; r2 = r3; i2 = i3;
+  }
 }
 
 __device__ __forceinline__ double clamp_norm(double v) {
@@ -144,9 +208,9 @@ __device__ __forceinline__ void scale_qp(const Team &tm, const QPView<T> &v, con
       a = group_max(a, rn.L) * v.D[j];
       if (rn.lane == 0) v.dx[j] = 1.0 / sqrt(clamp_norm(a));
     }
-    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
+    for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
       double a = 0.0;
-      for (int k = v.arp[i] + lane; k < v.arp[i + 1]; k += L)
+      for (int k = b + lane; k < e; k += L)
         a = fmax(a, fabs(v.araw[k]) * v.D[v.aci[k]]);
       a = group_max(a, L) * v.E[i];
       if (lane == 0) v.dy[i] = 1.0 / sqrt(clamp_norm(a));
@@ -352,39 +416,61 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
   return ok;
 }
 
-// d = K^-1 r by the Woodbury identity (FP64 inside, d rounded to T).
+// d = K^-1 r by the Woodbury identity (FP64 inside, d rounded to T).  With
+// an LDS stage (u and the scattered w in LDS, outside the part of s that
+// the triangular solve uses) the gathers of both passes hit LDS.
 template <class T>
 __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPView<T> &v,
-                                                     DenseLDS<double> &s, double rho_bar) {
+                                                     DenseLDS<double> &s, double rho_bar,
+                                                     double *stage = nullptr) {
   const int n = v.n, m = v.m, R = v.mr_cnt, ldS = v.ld;
+  const int n8 = (n + 7) & ~7;
   const LRLayout lo = lr_layout(n, m, R, ldS);
   const double *dinv = v.lr, *S = v.lr + lo.S, *Sinv = v.lr + lo.Sinv;
-  double *u = v.lr + lo.u, *wc = v.lr + lo.wc, *wr = v.lr + lo.wr;
+  double *wc = v.lr + lo.wc;
   auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
-  tm.sync();
-  for (int j = tm.tid; j < n; j += tm.nt) u[j] = dinv[j] * double(v.r[j]);
-  tm.sync();
-  // wc = B u over the multi-entry rows
-  const Rows rm(tm, v.lm);
-  for (int r = rm.g; r < R; r += rm.ng) {
-    const int i = v.mrows[r];
-    const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, u), rm.L);
-    if (rm.lane == 0) wc[r] = sqrt(rho_i(i)) * a;
-  }
-  tm.sync();
-  dense_solve_llt<double>(tm, s, S, ldS, R, Sinv, wc);
-  for (int r = tm.tid; r < R; r += tm.nt) {
-    const int i = v.mrows[r];
-    wr[i] = sqrt(rho_i(i)) * wc[r];
-  }
-  tm.sync();
-  // d = u - Delta^-1 B' w  (B' w through the rows of A'; zero on single-entry rows)
-  const Rows rn(tm, v.ln);
-  for (int j = rn.g; j < n; j += rn.ng) {
-    const double a = group_sum(row_partial<double>(v.atrp, v.atci, v.at64, j, rn.lane, rn.L, wr), rn.L);
-    if (rn.lane == 0) v.d[j] = T(u[j] - dinv[j] * a);
-  }
-  tm.sync();
+  auto body = [&](double *u, double *wr, bool zero_wr) __attribute__((always_inline)) {
+    tm.sync();
+    for (int j = tm.tid; j < n; j += tm.nt) u[j] = dinv[j] * double(v.r[j]);
+    if (zero_wr)
+      for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;
+    tm.sync();
+    // wc = B u over the multi-entry rows
+    const Rows rm(tm, v.lm);
+    // (rows of A with one entry have e - b <= 1 and are not in mrows; the
+    // pass visits only mrows, in the order of the compact index r)
+    {
+      int r = rm.g;
+      int i = r < R ? v.mrows[r] : 0;
+      int b = r < R ? v.arp[i] : 0, e = r < R ? v.arp[i + 1] : 0;
+      while (r < R) {
+        const int rn2 = r + rm.ng;
+        const int in = rn2 < R ? v.mrows[rn2] : 0;
+        const int bn = rn2 < R ? v.arp[in] : 0, en = rn2 < R ? v.arp[in + 1] : 0;
+        const double sr = sqrt(rho_i(i));
+        const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, rm.lane, rm.L, u), rm.L);
+        if (rm.lane == 0) wc[r] = sr * a;
+        r = rn2; i = in; b = bn; e = en;
+      }
+    }
+    tm.sync();
+    dense_solve_llt<double>(tm, s, S, ldS, R, Sinv, wc);
+    for (int r = tm.tid; r < R; r += tm.nt) {
+      const int i = v.mrows[r];
+      wr[i] = sqrt(rho_i(i)) * wc[r];
+    }
+    tm.sync();
+    // d = u - Delta^-1 B' w  (B' w through the rows of A'; zero on single-entry rows)
+    const Rows rn(tm, v.ln);
+    rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
+      const double uj = u[j], dj = dinv[j];
+      const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, wr), rn.L);
+      if (rn.lane == 0) v.d[j] = T(uj - dj * a);
+    });
+    tm.sync();
+  };
+  if (stage != nullptr && n8 + ((m + 7) & ~7) <= kStage) body(stage, stage + n8, true);
+  else body(v.lr + lo.u, v.lr + lo.wr, false);
 }
 
 // ------------------------------------------------------------------------
@@ -394,11 +480,13 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
 template <class T, class Team>
 __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, const DevSettings &set,
                          DenseLDS<T> *dl = nullptr, T *dB = nullptr, bool dense_ok = false,
-                         DenseLDS<double> *dl64 = nullptr, double *G = nullptr, bool lr_ok = false) {
+                         DenseLDS<double> *dl64 = nullptr, double *G = nullptr, bool lr_ok = false,
+                         double *stage = nullptr) {
+  QPState &S = *v.st;
   const int n = v.n, m = v.m;
   const T sigma = T(set.sigma);
-  const double c = v.st->c, cinv = 1.0 / c;
-  double rho_bar = v.st->rho_bar;
+  const double c = S.c, cinv = 1.0 / c;
+  double rho_bar = S.rho_bar;
   // rho_i in double for the iterate updates and residuals (the stored T copy
   // feeds only the PCG products)
   auto rho_of = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
@@ -426,17 +514,17 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   auto apply_pre = [&]() __attribute__((always_inline)) {
     if constexpr (std::is_same<Team, WGTeam>::value) {
       if (pre_kind == 1) precondition_dense(tm, v, *dl);
-      else precondition_lowrank(tm, v, *dl64, rho_bar);
+      else precondition_lowrank(tm, v, *dl64, rho_bar, stage);
     }
   };
   bool use_dense = false;
   if constexpr (std::is_same<Team, WGTeam>::value) {
     if (pre_kind != 0) {
       use_dense = true;
-      if (v.st->factor_rho != rho_bar) {
+      if (S.factor_rho != rho_bar) {
         ph = wall_clock64();
         use_dense = refactor();
-        if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
+        if (tm.tid == 0) S.factor_rho = use_dense ? rho_bar : 0.0;
         tm.sync();
         lap(c_factor);
       }
@@ -444,7 +532,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   }
 
   // initial iterate: continue, zeros, or the warm start of Section 6
-  const int mode = v.st->init_mode;
+  const int mode = S.init_mode;
   if (mode == 1) {
     for (int j = tm.tid; j < n; j += tm.nt) { v.x[j] = 0.0; v.xt[j] = 0.0; }
     for (int i = tm.tid; i < m; i += tm.nt) { v.z[i] = 0.0; v.y[i] = 0.0; }
@@ -455,8 +543,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     }
     for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = c * v.Einv[i] * v.yws[i];
     tm.sync();
-    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
-      const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, lane, L, v.x), L);
+    for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+      const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, v.x), L);
       if (lane == 0) v.z[i] = a;
     });
   } else {
@@ -466,8 +554,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   // zt = A xt ; s = rho (z - zt) - y  (feeds the first right-hand side);
   // both in double from the double copy of A (a mixed-precision refinement:
   // each linear solve starts from a residual computed in FP64)
-  for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
-    const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, lane, L, v.xt), L);
+  for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+    const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, v.xt), L);
     if (lane == 0) {
       v.zt64[i] = a;
       if (sizeof(T) == 4) v.zt[i] = T(a);
@@ -480,12 +568,19 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   bool have_check = false;
   double prs = 0.0, drs = 0.0, pnorm = 0.0, dnorm = 0.0, bnorm = -1.0;
   double res_prim = 0.0, res_dual = 0.0, eps_prim = 0.0, eps_dual = 0.0;
-  const double floor_rel = sizeof(T) == 4 ? 1e-6 : 1e-12;
   int bad = 0;
+  const double floor_rel = sizeof(T) == 4 ? 1e-6 : 1e-12;
   auto pcg_tol = [&](double b0) -> double {
     return have_check ? fmax(set.pcg_tol_frac * fmin(prs, drs), floor_rel * fmax(dnorm, 1e-30))
                       : 1e-3 * b0;
   };
+  // LDS staging of the vectors a pass gathers from (workgroup team): the
+  // gathers then hit LDS and only the streamed matrix comes from memory
+  const int n8 = (n + 7) & ~7, m8 = (m + 7) & ~7;
+  const bool stg_start = stage != nullptr && m8 + n8 <= kStage;
+  const bool stg_upd = stage != nullptr && n8 <= kStage;
+  const bool stg_kp = stage != nullptr && (int64_t)(n8 + m8) * (int64_t)sizeof(T) <= 8LL * kStage;
+  T *stT = reinterpret_cast<T *>(stage);
 
   ph = wall_clock64();
   while (true) {
@@ -494,21 +589,35 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     //     A xt = zt:  r = sigma (x - xt) - q - P xt + A' s
     double red[2];
     red[0] = 0.0; red[1] = 0.0;
-    for (int j = rn.g; j < n; j += rn.ng) {
-      double a = row_partial<double>(v.atrp, v.atci, v.at64, j, rn.lane, rn.L, v.s64) -
-                 row_partial<double>(v.prp, v.pci, v.p64, j, rn.lane, rn.L, v.xt);
-      a = group_sum(a, rn.L);
-      if (rn.lane == 0) {
-        const double r64 = set.sigma * (double(v.x[j]) - double(v.xt[j])) - v.q64[j] + a;
-        const T rj = T(r64);
-        v.r[j] = rj;
-        red[1] = fmax(red[1], fabs(r64));
-        if (!use_dense) {
-          const T dj = v.minv[j] * rj;
-          v.d[j] = dj; v.p[j] = dj;
-          red[0] += double(rj * dj);
+    auto start_pass = [&](const double *s_src, const double *x_src) __attribute__((always_inline)) {
+      rows_ahead2(v.atrp, v.prp, rn.g, rn.ng, n,
+                  [&](int j, int ab, int ae, int pb, int pe) __attribute__((always_inline)) {
+        // the row's own values are loaded before the gathers (they do not
+        // depend on them), so their latency overlaps
+        const double xj = v.x[j], xtj = v.xt[j], qj = v.q64[j];
+        double a = seg_partial<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, s_src) -
+                   seg_partial<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, x_src);
+        a = group_sum(a, rn.L);
+        if (rn.lane == 0) {
+          const double r64 = set.sigma * (xj - xtj) - qj + a;
+          const T rj = T(r64);
+          v.r[j] = rj;
+          red[1] = fmax(red[1], fabs(r64));
+          if (!use_dense) {
+            const T dj = v.minv[j] * rj;
+            v.d[j] = dj; v.p[j] = dj;
+            red[0] += double(rj * dj);
+          }
         }
-      }
+      });
+    };
+    if (stg_start) {
+      for (int i = tm.tid; i < m; i += tm.nt) stage[i] = v.s64[i];
+      for (int j = tm.tid; j < n; j += tm.nt) stage[m8 + j] = v.xt[j];
+      tm.sync();
+      start_pass(stage, stage + m8);
+    } else {
+      start_pass(v.s64, v.xt);
     }
     // the dense preconditioner is a factor of K itself: it is applied only
     // while the residual misses the tolerance (the PCG iterates are the same)
@@ -540,24 +649,34 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     const double tol = pcg_tol(bnorm);
     int it = 0;
     while (!dense_skip && rinf > tol && it < set.pcg_max_iter) {
-      // t = R A p
-      for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
-        const T a = group_sum(row_partial<T>(v.arp, v.aci, v.av, i, lane, L, v.p), L);
-        if (lane == 0) v.t[i] = v.rho[i] * a;
-      });
-      tm.sync();
-      // w = P p + sigma p + A' t ; p'w
-      red[0] = 0.0;
-      for (int j = rn.g; j < n; j += rn.ng) {
-        T a = row_partial<T>(v.prp, v.pci, v.pv, j, rn.lane, rn.L, v.p) +
-              row_partial<T>(v.atrp, v.atci, v.atv, j, rn.lane, rn.L, v.t);
-        a = group_sum(a, rn.L);
-        if (rn.lane == 0) {
+      // t = R A p ; w = P p + sigma p + A' t ; p'w
+      auto kprod = [&](const T *p_src, T *t_dst, const T *t_src) __attribute__((always_inline)) {
+        for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+          const T ri = v.rho[i];
+          const T a = group_sum(seg_partial<T>(v.aci, v.av, b, e, lane, L, p_src), L);
+          if (lane == 0) t_dst[i] = ri * a;
+        });
+        tm.sync();
+        red[0] = 0.0;
+        rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
+                    [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
           const T pj = v.p[j];
-          const T wj = a + sigma * pj;
-          v.w[j] = wj;
-          red[0] += double(pj * wj);
-        }
+          T a = seg_partial<T>(v.pci, v.pv, pb, pe, rn.lane, rn.L, p_src) +
+                seg_partial<T>(v.atci, v.atv, ab, ae, rn.lane, rn.L, t_src);
+          a = group_sum(a, rn.L);
+          if (rn.lane == 0) {
+            const T wj = a + sigma * pj;
+            v.w[j] = wj;
+            red[0] += double(pj * wj);
+          }
+        });
+      };
+      if (stg_kp) {
+        for (int j = tm.tid; j < n; j += tm.nt) stT[j] = v.p[j];
+        tm.sync();
+        kprod(stT, stT + n8, stT + n8);
+      } else {
+        kprod(v.p, v.t, v.t);
       }
       tm.template reduce<1, 0>(red);
       const double pw = red[0];
@@ -608,26 +727,32 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     // --- Algorithm 1 updates: x relaxed; v = alpha zt + (1-alpha) z + y/rho;
     //     z = Pi(v); y = rho (v - z)  (v-form of Section 3.3)
     for (int j = tm.tid; j < n; j += tm.nt) {
-      const double xn = set.alpha * v.xt[j] + (1.0 - set.alpha) * v.x[j];
+      const double xtj = v.xt[j];
+      const double xn = set.alpha * xtj + (1.0 - set.alpha) * v.x[j];
       if (do_check) v.dx[j] = xn - v.x[j];
       v.x[j] = xn;
+      if (stg_upd) stage[j] = xtj;
     }
-    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
-      const double a64 =
-          group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, lane, L, v.xt), L);
-      if (lane == 0) {
+    if (stg_upd) tm.sync();
+    auto upd_pass = [&](const double *xt_src) __attribute__((always_inline)) {
+      for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
         const double zi = v.z[i], yi = v.y[i], ri = rho_of(i);
-        const double vv = set.alpha * a64 + (1.0 - set.alpha) * zi + yi / ri;
-        const double zn = fmin(fmax(vv, v.l64[i]), v.u64[i]);
-        const double yn = ri * (vv - zn);
-        if (do_check) v.dy[i] = yn - yi;
-        if (sizeof(T) == 4) v.zt[i] = T(a64);
-        v.zt64[i] = a64;
-        v.z[i] = zn;
-        v.y[i] = yn;
-        v.s64[i] = ri * (zn - a64) - yn;
-      }
-    });
+        const double a64 = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, xt_src), L);
+        if (lane == 0) {
+          const double vv = set.alpha * a64 + (1.0 - set.alpha) * zi + yi / ri;
+          const double zn = fmin(fmax(vv, v.l64[i]), v.u64[i]);
+          const double yn = ri * (vv - zn);
+          if (do_check) v.dy[i] = yn - yi;
+          if (sizeof(T) == 4) v.zt[i] = T(a64);
+          v.zt64[i] = a64;
+          v.z[i] = zn;
+          v.y[i] = yn;
+          v.s64[i] = ri * (zn - a64) - yn;
+        }
+      });
+    };
+    if (stg_upd) upd_pass(stage);
+    else upd_pass(v.xt);
     tm.sync();
     lap(c_update);
     if (!do_check) continue;
@@ -644,9 +769,9 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     double chk[25];
 #pragma unroll
     for (int kk = 0; kk < 25; ++kk) chk[kk] = 0.0;
-    for_a_rows(tm, v, rm, [&](int i, int lane, int L) __attribute__((always_inline)) {
+    for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
       double ax = 0.0, adx = 0.0;
-      for (int kq = v.arp[i] + lane; kq < v.arp[i + 1]; kq += L) {
+      for (int kq = b + lane; kq < e; kq += L) {
         const double a = v.a64[kq];
         const int cj = v.aci[kq];
         ax += a * double(v.x[cj]);
@@ -752,7 +877,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         if constexpr (std::is_same<Team, WGTeam>::value) {
           if (pre_kind != 0) {
             use_dense = refactor();
-            if (tm.tid == 0) v.st->factor_rho = use_dense ? rho_bar : 0.0;
+            if (tm.tid == 0) S.factor_rho = use_dense ? rho_bar : 0.0;
             tm.sync();
             lap(c_factor);
           }
@@ -784,7 +909,6 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   }
   tm.template reduce<1, 0>(red);
   if (tm.tid == 0) {
-    QPState &S = *v.st;
     S.status = status;
     S.iter = k;
     S.pcg_iter = pcg_total;
@@ -797,8 +921,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     S.polish_status = 0;
     S.init_mode = 0;
     S.bad = bad;
-    S.solve_ms = double(wall_clock64() - t_start) * set.wall_tick_s * 1e3;
     const double tk = set.wall_tick_s * 1e3;
+    S.solve_ms = double(wall_clock64() - t_start) * tk;
     S.t_factor_ms = double(c_factor) * tk;
     S.t_pcg_ms = double(c_pcg) * tk;
     S.t_update_ms = double(c_update) * tk;
