@@ -7,8 +7,8 @@ Jacobi preconditioner, the ADMM iterations with their warm-started PCG
 solves, FP64 termination / infeasibility checks and rho adaptation,
 unscaling (and polishing when enabled), then the results copied to the host.
 
-Prints one JSON line (see the design doc for every field).  Only --gpus 1 is
-supported: this build uses a single GPU.
+Prints one JSON line.  Only --gpus 1 is supported: the library drives a
+single GPU.
 """
 from __future__ import annotations
 
@@ -44,28 +44,85 @@ def build_workload(name: str, count: int | None):
     return qps, desc, extra
 
 
-def algorithmic_bytes(qps, infos, check_every=25, value_bytes=4, index_bytes=4):
-    """Bytes the method must move per solve, summed over the batch: every
-    sparse matrix application reads its values and indices once, vectors are
-    read/written once per pass.  Per QP with a = nnz(A), p = nnz(P full):
-      PCG iteration  : A p, A'(R t), P p  -> 2a + p entries, vectors 12n + 4m
-      ADMM iteration : start pass (A', P) + update pass (A) -> 2a + p entries,
-                       vectors 10n + 16m
-      check (FP64)   : A, A', P in double -> 2a + p entries at 8+4 bytes,
-                       vectors 8 (4n + 4m)
+def algorithmic_bytes(qps, infos, value_bytes=4, check_every=25):
+    """Bytes the solve kernel must move, summed over the batch, counting each
+    matrix once per application at the width the path uses (index 4 B, FP64
+    value 8 B, working-precision value `value_bytes`) and each vector once per
+    pass.  Per QP with a = nnz(A), p = nnz(P full), a_m = entries of the rows
+    of A with several entries (R of them), n, m:
+      ADMM iteration (FP64): start pass A', P -> 12 (a + p) + 4 (2n) + 8 (5n + m);
+                             update pass A    -> 12 a + 4 m + 8 (3n + 9m)
+      PCG iteration (T)    : A, A', P -> (4 + vb)(2a + p) + 4 (2n + m) + vb (5n + 2m) + 16 n
+      preconditioner apply : low-rank -> 12 (a_m + a) + 8 (R^2 + 3n + 2m);
+                             dense    -> vb n^2 (two triangular sweeps) + vb 2n;
+                             Jacobi   -> in the PCG vectors
+        (applies = ADMM iterations + inner PCG iterations beyond the first)
+      check (FP64, every 25): 12 (2a + p) + 8 (6n + 6m)
+      factorisation (1 + rho updates): low-rank -> 8 (2 R n + R^2);
+                                       dense    -> vb (3 n^2)
     """
-    e = value_bytes + index_bytes
+    vb = value_bytes
     total = 0.0
     for qp, info in zip(qps, infos):
         n, m = qp.n, qp.m
         a = qp.A.nnz
         p = 2 * qp.P.nnz - int((qp.P.diagonal() != 0).sum())
-        pcg = info["pcg_iter"] * (e * (2 * a + p) + 4 * (12 * n + 4 * m))
-        admm = info["iter"] * (e * (2 * a + p) + 4 * (10 * n + 16 * m))
-        checks = -(-info["iter"] // check_every)
-        chk = checks * ((8 + index_bytes) * (2 * a + p) + 8 * (4 * n + 4 * m))
-        total += pcg + admm + chk
-    return total
+        rl = np.diff(qp.A.indptr)
+        am = int(rl[rl >= 2].sum())
+        R = int((rl >= 2).sum())
+        it, pcg = info["iter"], info["pcg_iter"]
+        admm = it * (12 * (a + p) + 8 * n + 8 * (5 * n + m) + 12 * a + 4 * m + 8 * (3 * n + 9 * m))
+        inner = pcg * ((4 + vb) * (2 * a + p) + 4 * (2 * n + m) + vb * (5 * n + 2 * m) + 16 * n)
+        applies = it + max(0, pcg - it)
+        path = info.get("linsys", 1)
+        if path == 3:
+            apply_b = 12 * (am + a) + 8 * (R * R + 3 * n + 2 * m)
+            fact_b = 8 * (2 * R * n + R * R)
+        elif path == 2:
+            apply_b = vb * n * n + vb * 2 * n
+            fact_b = vb * 3 * n * n
+        else:
+            apply_b, fact_b = 0, 0
+        checks = -(-it // check_every)
+        chk = checks * (12 * (2 * a + p) + 8 * (6 * n + 6 * m))
+        total += admm + inner + applies * apply_b + chk + (1 + info["rho_updates"]) * fact_b
+    return float(total)
+
+
+def kernel_source_sha256() -> str:
+    """Hash of the kernel sources (csrc/*.h, csrc/*.hip), to tie a stored
+    counter measurement to the code it was taken on."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1711_08013_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per solve launch from the committed counter summary of this
+    workload, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"solve_wg_kernel_{workload}1024_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and line.split("=")[0].strip() in ("traffic_bytes_per_launch",
+                                                              "kernel_source_sha256"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(qps, budget_s: float, extra: dict):
@@ -120,7 +177,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+              "a multi-GPU run is not supported", file=sys.stderr)
         sys.exit(2)
 
     import paper_1711_08013_amd as pm
@@ -161,8 +218,9 @@ def main():
     algo = algorithmic_bytes(qps, infos)
     kms = float(np.mean(kernel_ms))
     achieved = algo / (kms * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload) if args.count is None else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "solve_wg_kernel<float>", "kernel_ms": round(kms, 3),
                 "algorithmic_bytes": algo}
 

@@ -16,8 +16,8 @@
  *   finish  : unscaling (Section 5.1), solution polishing with regularisation
  *             and iterative refinement (Section 4).
  *
- * Readings of points the paper leaves open are listed in the design doc; each is
- * marked "reading" where it is applied.
+ * Where the paper leaves a point open, the reading taken is marked "reading"
+ * where it is applied.
  */
 #include "oracle.h"
 

@@ -23,6 +23,8 @@
 
 namespace osqpmi {
 
+constexpr int kMaxPolishWaves = 16;   // polishing workgroups have at most 1024 threads
+
 // Workspace (doubles) of one polishing slot.  Dense: M (n x ldm), the
 // inverses of its 64 x 64 diagonal blocks, B (rmax x n).  Low-rank: Delta^-1,
 // u, S (rmax x ldS), its block inverses, w compact, w by row, G (rmax x ldg).
@@ -80,33 +82,59 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     bact[i] = a < 0.0 ? v.l64[i] : (a > 0.0 ? v.u64[i] : 0.0);
   }
   tm.sync();
-  if (tm.tid == 0) {
-    int R = 0;
-    for (int i = 0; i < m; ++i)
-      if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] >= 2) multi[R++] = i;
-    R_sh = R;
+  // active multi-entry rows, in row order: a ballot per wave, the waves'
+  // counts in LDS, then each thread's position (deterministic)
+  __shared__ int wcount[kMaxPolishWaves];
+  if (tm.tid == 0) R_sh = 0;
+  {
+    const int lane = tm.tid & (kWave - 1), wv = tm.tid >> 6, nw = tm.nt >> 6;
+    for (int r0 = 0; r0 < v.mr_cnt; r0 += tm.nt) {
+      const int r = r0 + tm.tid;
+      const int i = r < v.mr_cnt ? v.mrows[r] : 0;
+      const bool f = r < v.mr_cnt && act[i] != 0.0;
+      const unsigned long long bal = __ballot(f);
+      const int below = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) wcount[wv] = __popcll(bal);
+      tm.sync();
+      int off = R_sh;
+      for (int w = 0; w < wv; ++w) off += wcount[w];
+      if (f) multi[off + below] = i;
+      tm.sync();
+      if (tm.tid == 0) {
+        int t = R_sh;
+        for (int w = 0; w < nw; ++w) t += wcount[w];
+        R_sh = t;
+      }
+      tm.sync();
+    }
   }
-  tm.sync();
   const int R = min(R_sh, rmax);
+  const Rows rn(tm, v.ln), rm(tm, v.lm);
   bool ok_fact;
   if (lowrank) {
     // Delta = diag(P) + d + single-entry active rows a^2 / d;  G = B Delta^-1/2
-    for (int j = tm.tid; j < n; j += tm.nt) {
-      double a = delta;
-      for (int k = v.prp[j]; k < v.prp[j + 1]; ++k)
-        if (v.pci[k] == j) a += v.p64[k];
-      for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
-        const int i = v.atci[k];
-        if (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] == 1) a += v.at64[k] * v.at64[k] * dinv_d;
-      }
-      Dl[j] = 1.0 / a;
-    }
+    // ry (free until the refinement) marks the single-entry active rows
+    for (int i = tm.tid; i < m; i += tm.nt)
+      ry[i] = (act[i] != 0.0 && v.arp[i + 1] - v.arp[i] == 1) ? 1.0 : 0.0;
     for (size_t e = tm.tid; e < (size_t)R * n8; e += tm.nt) G[e] = 0.0;
     for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;
     tm.sync();
-    for (int r = tm.tid; r < R; r += tm.nt) {
+    rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
+                [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
+      double a = 0.0;
+      for (int k = pb + rn.lane; k < pe; k += rn.L)
+        if (v.pci[k] == j) a += v.p64[k];
+      for (int k = ab + rn.lane; k < ae; k += rn.L) {
+        const double e = v.at64[k];
+        a += ry[v.atci[k]] * e * e * dinv_d;
+      }
+      a = group_sum(a, rn.L);
+      if (rn.lane == 0) Dl[j] = 1.0 / (delta + a);
+    });
+    tm.sync();
+    for (int r = rm.g; r < R; r += rm.ng) {
       const int i = multi[r];
-      for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) {
+      for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L) {
         const int j = v.aci[k];
         G[(size_t)r * n8 + j] = v.a64[k] * rs * sqrt(Dl[j]);
       }
@@ -150,74 +178,69 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     if (lowrank) {
       for (int j = tm.tid; j < n; j += tm.nt) u[j] = Dl[j] * g[j];
       tm.sync();
-      for (int r = tm.tid; r < R; r += tm.nt) {
+      for (int r = rm.g; r < R; r += rm.ng) {
         const int i = multi[r];
-        double a = 0.0;
-        for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * u[v.aci[k]];
-        wc[r] = rs * a;
+        const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, u), rm.L);
+        if (rm.lane == 0) wc[r] = rs * a;
       }
       tm.sync();
       dense_solve_llt<double>(tm, s, S, r8, R, Sinv, wc);
       for (int r = tm.tid; r < R; r += tm.nt) wr[multi[r]] = rs * wc[r];
       tm.sync();
-      for (int j = tm.tid; j < n; j += tm.nt) {
-        double a = 0.0;
-        for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) a += v.at64[k] * wr[v.atci[k]];
-        g[j] = u[j] - Dl[j] * a;
-      }
+      rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
+        const double uj = u[j], dj = Dl[j];
+        const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, wr), rn.L);
+        if (rn.lane == 0) g[j] = uj - dj * a;
+      });
       tm.sync();
     } else {
       dense_solve_llt<double>(tm, s, M, n8, n, Minv, g);
     }
   };
   // first solve: rhs = -q + A_a' b_a / d
-  for (int j = tm.tid; j < n; j += tm.nt) {
-    double a = 0.0;
-    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
-      const int i = v.atci[k];
-      a += v.at64[k] * bact[i];     // bact is 0 on inactive rows
-    }
-    g[j] = -v.q64[j] + a * dinv_d;
-  }
+  // (bact is 0 on inactive rows)
+  rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
+    const double qj = v.q64[j];
+    const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, bact), rn.L);
+    if (rn.lane == 0) g[j] = -qj + a * dinv_d;
+  });
   tm.sync();
   msolve();
   for (int j = tm.tid; j < n; j += tm.nt) tx[j] = g[j];
   tm.sync();
-  for (int i = tm.tid; i < m; i += tm.nt) {
-    double a = 0.0;
-    if (act[i] != 0.0)
-      for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * tx[v.aci[k]];
-    ty[i] = act[i] != 0.0 ? (a - bact[i]) * dinv_d : 0.0;
-  }
+  for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+    const double ai = act[i], bi = bact[i];
+    const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, tx), L);
+    if (lane == 0) ty[i] = ai != 0.0 ? (a - bi) * dinv_d : 0.0;
+  });
   tm.sync();
   // iterative refinement: t += (K + dK)^-1 (g - K t), K without d
   for (int it = 0; it < set.refine; ++it) {
-    for (int i = tm.tid; i < m; i += tm.nt) {
-      double a = 0.0;
-      if (act[i] != 0.0)
-        for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * tx[v.aci[k]];
-      ry[i] = act[i] != 0.0 ? bact[i] - a : 0.0;
-    }
-    for (int j = tm.tid; j < n; j += tm.nt) {
-      double a = 0.0;
-      for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) a += v.p64[k] * tx[v.pci[k]];
-      for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) a += v.at64[k] * ty[v.atci[k]];
-      rx[j] = -v.q64[j] - a;
-    }
+    for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+      const double ai = act[i], bi = bact[i];
+      const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, tx), L);
+      if (lane == 0) ry[i] = ai != 0.0 ? bi - a : 0.0;
+    });
+    rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
+                [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
+      const double qj = v.q64[j];
+      const double a = group_sum(seg_partial<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx) +
+                                 seg_partial<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
+      if (rn.lane == 0) rx[j] = -qj - a;
+    });
     tm.sync();
-    for (int j = tm.tid; j < n; j += tm.nt) {
-      double a = 0.0;
-      for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) a += v.at64[k] * ry[v.atci[k]];
-      g[j] = rx[j] + a * dinv_d;
-    }
+    rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
+      const double rxj = rx[j];
+      const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, ry), rn.L);
+      if (rn.lane == 0) g[j] = rxj + a * dinv_d;
+    });
     tm.sync();
     msolve();
-    for (int i = tm.tid; i < m; i += tm.nt) {
-      double a = 0.0;
-      if (act[i] != 0.0)
-        for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) a += v.a64[k] * g[v.aci[k]];
-      if (act[i] != 0.0) ty[i] += (a - ry[i]) * dinv_d;
-    }
+    for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+      const double ai = act[i], ri = ry[i];
+      const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, g), L);
+      if (lane == 0 && ai != 0.0) ty[i] += (a - ri) * dinv_d;
+    });
     tm.sync();
     for (int j = tm.tid; j < n; j += tm.nt) tx[j] += g[j];
     tm.sync();
@@ -226,31 +249,34 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   double red[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) red[k] = 0.0;
-  for (int i = tm.tid; i < m; i += tm.nt) {
-    double ax = 0.0;
-    for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) ax += v.a64[k] * tx[v.aci[k]];
-    const double z = fmin(fmax(ax, v.l64[i]), v.u64[i]);
-    ry[i] = z;   // keep z
-    const double e = v.Einv[i];
-    red[1] = fmax(red[1], fabs(e * (ax - z)));
-    red[2] = fmax(red[2], fabs(e * ax));
-    red[3] = fmax(red[3], fabs(e * z));
-    // sign flag folded in with fmax (a conditional store of the constant
-    // was dropped by hipcc's backend in this loop)
-    const bool flip = (act[i] < 0.0 && ty[i] > 0.0) || (act[i] > 0.0 && ty[i] < 0.0);
-    red[8] = fmax(red[8], flip ? 1.0 : 0.0);
-  }
-  for (int j = tm.tid; j < n; j += tm.nt) {
-    double px = 0.0, aty = 0.0;
-    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) px += v.p64[k] * tx[v.pci[k]];
-    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) aty += v.at64[k] * ty[v.atci[k]];
-    const double d = v.Dinv[j], q = v.q64[j];
-    red[0] += 0.5 * tx[j] * px + q * tx[j];
-    red[4] = fmax(red[4], fabs(d * (px + q + aty)));
-    red[5] = fmax(red[5], fabs(d * px));
-    red[6] = fmax(red[6], fabs(d * aty));
-    red[7] = fmax(red[7], fabs(d * q));
-  }
+  for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+    const double lo = v.l64[i], hi = v.u64[i], ei = v.Einv[i], ai = act[i], tyi = ty[i];
+    const double ax = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, tx), L);
+    if (lane == 0) {
+      const double z = fmin(fmax(ax, lo), hi);
+      ry[i] = z;   // keep z
+      red[1] = fmax(red[1], fabs(ei * (ax - z)));
+      red[2] = fmax(red[2], fabs(ei * ax));
+      red[3] = fmax(red[3], fabs(ei * z));
+      // sign flag folded in with fmax (a conditional store of the constant
+      // was dropped by hipcc's backend in this loop)
+      const bool flip = (ai < 0.0 && tyi > 0.0) || (ai > 0.0 && tyi < 0.0);
+      red[8] = fmax(red[8], flip ? 1.0 : 0.0);
+    }
+  });
+  rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
+              [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
+    const double d = v.Dinv[j], q = v.q64[j], txj = tx[j];
+    const double px = group_sum(seg_partial<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx), rn.L);
+    const double aty = group_sum(seg_partial<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
+    if (rn.lane == 0) {
+      red[0] += 0.5 * txj * px + q * txj;
+      red[4] = fmax(red[4], fabs(d * (px + q + aty)));
+      red[5] = fmax(red[5], fabs(d * px));
+      red[6] = fmax(red[6], fabs(d * aty));
+      red[7] = fmax(red[7], fabs(d * q));
+    }
+  });
   tm.template reduce<1, 8>(red);
   const double prim = red[1], dual = cinv * red[4];
   const bool finite = isfinite(prim) && isfinite(dual) && isfinite(red[0]);

@@ -81,9 +81,9 @@ struct Rows {
 };
 
 // Partial dot over the lanes of a group of sum_k v[k] x[ci[k]], k in [b, e)
-// (not reduced).  Each round gathers eight entries per lane with predicated
-// loads, all in flight together: the passes are bound by memory latency per
-// wave, not by arithmetic, and a row needs ceil(len / 8L) rounds.
+// (not reduced).  Each round gathers eight entries per lane, all in flight
+// together: the passes are bound by memory latency per wave, not by
+// arithmetic, and a row needs ceil(len / 8L) rounds.
 template <class A, class V, class X>
 __device__ __forceinline__ A seg_partial(const int *ci, const V *v, int b, int e, int lane, int L,
                                          const X *x) {
@@ -239,42 +239,46 @@ __device__ __forceinline__ void scale_qp(const Team &tm, const QPView<T> &v, con
   }
   // write the scaled problem: Pbar = c D P D, qbar = c D q, Abar = E A D,
   // lbar = E l, ubar = E u
+  // (columns of P without a diagonal entry keep pdiag = 0)
   for (int j = tm.tid; j < n; j += tm.nt) {
     const double Dj = v.D[j];
-    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) {
-      const double val = c * (v.praw[k] * Dj) * v.D[v.pci[k]];
-      v.p64[k] = val;
-      v.pv[k] = T(val);
-      if (v.pci[k] == j) v.pdiag[j] = T(val);
-    }
-    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
-      const double val = scale_a(v.atraw[k], v.E[v.atci[k]], Dj);
-      v.at64[k] = val;
-      v.atv[k] = T(val);
-    }
     const double qq = c * Dj * v.qraw[j];
     v.q64[j] = qq;
     v.q[j] = T(qq);
     v.Dinv[j] = 1.0 / Dj;
+    v.pdiag[j] = T(0);
   }
   for (int i = tm.tid; i < m; i += tm.nt) {
     const double Ei = v.E[i];
-    for (int k = v.arp[i]; k < v.arp[i + 1]; ++k) {
-      const double val = scale_a(v.araw[k], Ei, v.D[v.aci[k]]);
-      v.a64[k] = val;
-      v.av[k] = T(val);
-    }
     const double lo = v.lraw[i] * Ei, hi = v.uraw[i] * Ei;
     v.l64[i] = lo; v.u64[i] = hi;
     v.l[i] = T(lo); v.u[i] = T(hi);
     v.Einv[i] = 1.0 / Ei;
   }
-  // P without a diagonal entry in column j: pdiag = 0
-  for (int j = tm.tid; j < n; j += tm.nt) {
-    bool has = false;
-    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k) has |= (v.pci[k] == j);
-    if (!has) v.pdiag[j] = T(0);
-  }
+  tm.sync();
+  rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
+              [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
+    const double Dj = v.D[j];
+    for (int k = pb + rn.lane; k < pe; k += rn.L) {
+      const double val = c * (v.praw[k] * Dj) * v.D[v.pci[k]];
+      v.p64[k] = val;
+      v.pv[k] = T(val);
+      if (v.pci[k] == j) v.pdiag[j] = T(val);
+    }
+    for (int k = ab + rn.lane; k < ae; k += rn.L) {
+      const double val = scale_a(v.atraw[k], v.E[v.atci[k]], Dj);
+      v.at64[k] = val;
+      v.atv[k] = T(val);
+    }
+  });
+  for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+    const double Ei = v.E[i];
+    for (int k = b + lane; k < e; k += L) {
+      const double val = scale_a(v.araw[k], Ei, v.D[v.aci[k]]);
+      v.a64[k] = val;
+      v.av[k] = T(val);
+    }
+  });
   if (tm.tid == 0) v.st->c = c;
   tm.sync();
 }

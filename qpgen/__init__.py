@@ -6,7 +6,7 @@ by the tests, the benchmark and the oracle's checks.  Every generator draws from
 ``numpy.random.default_rng(SeedSequence([cfg, index]))`` so that a (cfg, index)
 pair always names the same instance.
 
-Conventions (all readings are listed in the design doc):
+Conventions:
 
 * Matrices are returned as ``scipy.sparse.csr_matrix`` with float64 values and
   sorted column indices; ``P`` is the upper triangle (diagonal included).

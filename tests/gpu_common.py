@@ -8,7 +8,7 @@ from tests import qpcheck
 # objective parity bar: |f_gpu - f_oracle| <= 1e-3 max(1, |f_oracle|)
 OBJ_TOL = 1e-3
 # the z-free primal ratio may exceed the device's z-based one by eps_rel
-# (its tolerance uses ||Pi(Ax)|| instead of ||z||); see the design doc
+# (its tolerance uses ||Pi(Ax)|| instead of ||z||)
 PRIM_SLACK = 1.0 + 2e-3
 DUAL_SLACK = 1.0 + 1e-9
 
