@@ -389,11 +389,11 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
   for (int j = tm.tid; j < n; j += tm.nt) {
     double a = sigma;
     for (int k = v.prp[j]; k < v.prp[j + 1]; ++k)
-      if (v.pci[k] == j) a += v.p64[k];
+      if (v.pci[k] == j) a += double(v.pv[k]);
     for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
       const int i = v.atci[k];
       if (v.arp[i + 1] - v.arp[i] == 1) {
-        const double e = v.at64[k];
+        const double e = double(v.atv[k]);
         a += rho_i(i) * e * e;
       }
     }
@@ -408,7 +408,7 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
     const double sr = sqrt(rho_i(i));
     for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L) {
       const int j = v.aci[k];
-      G[(size_t)r * ldg + j] = sr * v.a64[k] * sqrt(dinv[j]);
+      G[(size_t)r * ldg + j] = sr * double(v.av[k]) * sqrt(dinv[j]);
     }
   }
   tm.sync();
@@ -420,29 +420,36 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
   return ok;
 }
 
-// d = K^-1 r by the Woodbury identity (FP64 inside, d rounded to T).  With
-// an LDS stage (u and the scattered w in LDS, outside the part of s that
-// the triangular solve uses) the gathers of both passes hit LDS.
+// K^-1 r by the Woodbury identity, FP64 inside (the matrix values are the
+// working-precision copies the other passes use, so the inverse is exact for
+// the same K).  u = Delta^-1 r is formed here from r (T), or was left in the
+// block's u by the caller (u_ready, from the FP64 residual).  The result goes
+// to d (rounded to T) or, to_xt, is added to the FP64 iterate x~ (the direct
+// solve).  With an LDS stage (u and the scattered w in LDS, outside the part
+// of s that the triangular solve uses) the gathers of both passes hit LDS.
 template <class T>
 __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPView<T> &v,
                                                      DenseLDS<double> &s, double rho_bar,
-                                                     double *stage = nullptr) {
+                                                     double *stage = nullptr, bool u_ready = false,
+                                                     bool to_xt = false) {
   const int n = v.n, m = v.m, R = v.mr_cnt, ldS = v.ld;
   const int n8 = (n + 7) & ~7;
   const LRLayout lo = lr_layout(n, m, R, ldS);
   const double *dinv = v.lr, *S = v.lr + lo.S, *Sinv = v.lr + lo.Sinv;
-  double *wc = v.lr + lo.wc;
+  double *wc = v.lr + lo.wc, *ug = v.lr + lo.u;
   auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
   auto body = [&](double *u, double *wr, bool zero_wr) __attribute__((always_inline)) {
     tm.sync();
-    for (int j = tm.tid; j < n; j += tm.nt) u[j] = dinv[j] * double(v.r[j]);
+    if (!u_ready) {
+      for (int j = tm.tid; j < n; j += tm.nt) u[j] = dinv[j] * double(v.r[j]);
+    } else if (u != ug) {
+      for (int j = tm.tid; j < n; j += tm.nt) u[j] = ug[j];
+    }
     if (zero_wr)
       for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;
     tm.sync();
     // wc = B u over the multi-entry rows
     const Rows rm(tm, v.lm);
-    // (rows of A with one entry have e - b <= 1 and are not in mrows; the
-    // pass visits only mrows, in the order of the compact index r)
     {
       int r = rm.g;
       int i = r < R ? v.mrows[r] : 0;
@@ -452,7 +459,7 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
         const int in = rn2 < R ? v.mrows[rn2] : 0;
         const int bn = rn2 < R ? v.arp[in] : 0, en = rn2 < R ? v.arp[in + 1] : 0;
         const double sr = sqrt(rho_i(i));
-        const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, rm.lane, rm.L, u), rm.L);
+        const double a = group_sum(seg_partial<double>(v.aci, v.av, b, e, rm.lane, rm.L, u), rm.L);
         if (rm.lane == 0) wc[r] = sr * a;
         r = rn2; i = in; b = bn; e = en;
       }
@@ -464,17 +471,22 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
       wr[i] = sqrt(rho_i(i)) * wc[r];
     }
     tm.sync();
-    // d = u - Delta^-1 B' w  (B' w through the rows of A'; zero on single-entry rows)
+    // K^-1 r = u - Delta^-1 B' w  (B' w through the rows of A'; zero on
+    // single-entry rows)
     const Rows rn(tm, v.ln);
     rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
       const double uj = u[j], dj = dinv[j];
-      const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, wr), rn.L);
-      if (rn.lane == 0) v.d[j] = T(uj - dj * a);
+      const double a = group_sum(seg_partial<double>(v.atci, v.atv, b, e, rn.lane, rn.L, wr), rn.L);
+      if (rn.lane == 0) {
+        const double step = uj - dj * a;
+        if (to_xt) v.xt[j] += step;
+        else v.d[j] = T(step);
+      }
     });
     tm.sync();
   };
   if (stage != nullptr && n8 + ((m + 7) & ~7) <= kStage) body(stage, stage + n8, true);
-  else body(v.lr + lo.u, v.lr + lo.wr, false);
+  else body(ug, v.lr + lo.wr, false);
 }
 
 // ------------------------------------------------------------------------
@@ -548,7 +560,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = c * v.Einv[i] * v.yws[i];
     tm.sync();
     for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
-      const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, v.x), L);
+      const double a = group_sum(seg_partial<double>(v.aci, v.av, b, e, lane, L, v.x), L);
       if (lane == 0) v.z[i] = a;
     });
   } else {
@@ -559,7 +571,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   // both in double from the double copy of A (a mixed-precision refinement:
   // each linear solve starts from a residual computed in FP64)
   for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
-    const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, v.xt), L);
+    const double a = group_sum(seg_partial<double>(v.aci, v.av, b, e, lane, L, v.xt), L);
     if (lane == 0) {
       v.zt64[i] = a;
       if (sizeof(T) == 4) v.zt[i] = T(a);
@@ -586,8 +598,13 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   const bool stg_kp = stage != nullptr && (int64_t)(n8 + m8) * (int64_t)sizeof(T) <= 8LL * kStage;
   T *stT = reinterpret_cast<T *>(stage);
 
+  // the low-rank form solves K exactly in FP64: there the step is the direct
+  // one (Section 3.1 with the reduced matrix), x~ += K^-1 r, and no PCG runs
+  const int64_t lr_u = pre_kind == 2 ? lr_layout(n, m, v.mr_cnt, v.ld).u : 0;
+
   ph = wall_clock64();
   while (true) {
+    const bool direct = pre_kind == 2 && use_dense;
     // --- PCG start: r = b - K xt with b = sigma x - q + A'(rho z - y)
     //     (Section 3.1, indirect method), K = P + sigma I + A' R A, using
     //     A xt = zt:  r = sigma (x - xt) - q - P xt + A' s
@@ -599,13 +616,14 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         // the row's own values are loaded before the gathers (they do not
         // depend on them), so their latency overlaps
         const double xj = v.x[j], xtj = v.xt[j], qj = v.q64[j];
-        double a = seg_partial<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, s_src) -
-                   seg_partial<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, x_src);
+        double a = seg_partial<double>(v.atci, v.atv, ab, ae, rn.lane, rn.L, s_src) -
+                   seg_partial<double>(v.pci, v.pv, pb, pe, rn.lane, rn.L, x_src);
         a = group_sum(a, rn.L);
         if (rn.lane == 0) {
           const double r64 = set.sigma * (xj - xtj) - qj + a;
           const T rj = T(r64);
           v.r[j] = rj;
+          if (direct) v.lr[lr_u + j] = v.lr[j] * r64;   // u = Delta^-1 r in FP64
           red[1] = fmax(red[1], fabs(r64));
           if (!use_dense) {
             const T dj = v.minv[j] * rj;
@@ -630,7 +648,9 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       if (use_dense) {
         tm.template reduce<0, 1>(red + 1);
         dense_skip = bnorm >= 0.0 && red[1] <= pcg_tol(bnorm);
-        if (!dense_skip) {
+        if (direct) {
+          if (!dense_skip) precondition_lowrank(tm, v, *dl64, rho_bar, stage, true, true);
+        } else if (!dense_skip) {
           apply_pre();
           for (int j = tm.tid; j < n; j += tm.nt) {
             const T dj = v.d[j];
@@ -651,8 +671,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     // check, floored relative to the dual normaliser; 1e-3 of the first
     // residual before the first check
     const double tol = pcg_tol(bnorm);
-    int it = 0;
-    while (!dense_skip && rinf > tol && it < set.pcg_max_iter) {
+    int it = (direct && !dense_skip) ? 1 : 0;
+    while (!direct && !dense_skip && rinf > tol && it < set.pcg_max_iter) {
       // t = R A p ; w = P p + sigma p + A' t ; p'w
       auto kprod = [&](const T *p_src, T *t_dst, const T *t_src) __attribute__((always_inline)) {
         for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
@@ -741,7 +761,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     auto upd_pass = [&](const double *xt_src) __attribute__((always_inline)) {
       for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
         const double zi = v.z[i], yi = v.y[i], ri = rho_of(i);
-        const double a64 = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, xt_src), L);
+        const double a64 = group_sum(seg_partial<double>(v.aci, v.av, b, e, lane, L, xt_src), L);
         if (lane == 0) {
           const double vv = set.alpha * a64 + (1.0 - set.alpha) * zi + yi / ri;
           const double zn = fmin(fmax(vv, v.l64[i]), v.u64[i]);
