@@ -94,10 +94,10 @@ int check_settings(const osqp_settings &s) {
 }
 
 int pow2_lanes(double avg) {
-  // lanes per row: about an eighth of the average row length (two four-wide
-  // gather rounds per lane), a power of two in [1, 64]
+  // lanes per row: about a sixteenth of the average row length (one round of
+  // four 16-byte chunks per lane), a power of two in [1, 64]
   int L = 1;
-  while (L < 64 && 8.0 * L < avg) L <<= 1;
+  while (L < 64 && 16.0 * L < avg) L <<= 1;
   return L;
 }
 
@@ -483,7 +483,11 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     d.lm = pow2_lanes(multi_cnt > 0 ? double(multi_nnz) / double(multi_cnt) : 1.0);
     d.ln = pow2_lanes(double(pfull_nnz[k] + p.A.nnz) / p.n);
     d.dense_off = 0;
-    b->sum_n += p.n; b->sum_m += p.m; b->nnz_a += p.A.nnz; b->nnz_p += pfull_nnz[k];
+    // entry ranges start on multiples of 4, so 16-byte loads of four
+    // entries stay aligned (the gap entries are zero and never counted)
+    b->sum_n += p.n; b->sum_m += p.m;
+    b->nnz_a += (p.A.nnz + 3) & ~int64_t(3);
+    b->nnz_p += (pfull_nnz[k] + 3) & ~int64_t(3);
   }
   // which QPs get the whole grid: large enough that one workgroup would be
   // the bottleneck of the batch

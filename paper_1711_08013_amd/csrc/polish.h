@@ -189,7 +189,7 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       tm.sync();
       rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
         const double uj = u[j], dj = Dl[j];
-        const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, wr), rn.L);
+        const double a = group_sum(seg_partial4<double>(v.atci, v.at64, b, e, rn.lane, rn.L, wr), rn.L);
         if (rn.lane == 0) g[j] = uj - dj * a;
       });
       tm.sync();
@@ -201,7 +201,7 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   // (bact is 0 on inactive rows)
   rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
     const double qj = v.q64[j];
-    const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, bact), rn.L);
+    const double a = group_sum(seg_partial4<double>(v.atci, v.at64, b, e, rn.lane, rn.L, bact), rn.L);
     if (rn.lane == 0) g[j] = -qj + a * dinv_d;
   });
   tm.sync();
@@ -210,7 +210,7 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   tm.sync();
   for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
     const double ai = act[i], bi = bact[i];
-    const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, tx), L);
+    const double a = group_sum(seg_partial4<double>(v.aci, v.a64, b, e, lane, L, tx), L);
     if (lane == 0) ty[i] = ai != 0.0 ? (a - bi) * dinv_d : 0.0;
   });
   tm.sync();
@@ -218,27 +218,27 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   for (int it = 0; it < set.refine; ++it) {
     for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
       const double ai = act[i], bi = bact[i];
-      const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, tx), L);
+      const double a = group_sum(seg_partial4<double>(v.aci, v.a64, b, e, lane, L, tx), L);
       if (lane == 0) ry[i] = ai != 0.0 ? bi - a : 0.0;
     });
     rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
                 [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
       const double qj = v.q64[j];
-      const double a = group_sum(seg_partial<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx) +
-                                 seg_partial<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
+      const double a = group_sum(seg_partial4<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx) +
+                                 seg_partial4<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
       if (rn.lane == 0) rx[j] = -qj - a;
     });
     tm.sync();
     rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
       const double rxj = rx[j];
-      const double a = group_sum(seg_partial<double>(v.atci, v.at64, b, e, rn.lane, rn.L, ry), rn.L);
+      const double a = group_sum(seg_partial4<double>(v.atci, v.at64, b, e, rn.lane, rn.L, ry), rn.L);
       if (rn.lane == 0) g[j] = rxj + a * dinv_d;
     });
     tm.sync();
     msolve();
     for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
       const double ai = act[i], ri = ry[i];
-      const double a = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, g), L);
+      const double a = group_sum(seg_partial4<double>(v.aci, v.a64, b, e, lane, L, g), L);
       if (lane == 0 && ai != 0.0) ty[i] += (a - ri) * dinv_d;
     });
     tm.sync();
@@ -251,7 +251,7 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   for (int k = 0; k < 9; ++k) red[k] = 0.0;
   for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
     const double lo = v.l64[i], hi = v.u64[i], ei = v.Einv[i], ai = act[i], tyi = ty[i];
-    const double ax = group_sum(seg_partial<double>(v.aci, v.a64, b, e, lane, L, tx), L);
+    const double ax = group_sum(seg_partial4<double>(v.aci, v.a64, b, e, lane, L, tx), L);
     if (lane == 0) {
       const double z = fmin(fmax(ax, lo), hi);
       ry[i] = z;   // keep z
@@ -267,8 +267,8 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
               [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
     const double d = v.Dinv[j], q = v.q64[j], txj = tx[j];
-    const double px = group_sum(seg_partial<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx), rn.L);
-    const double aty = group_sum(seg_partial<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
+    const double px = group_sum(seg_partial4<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx), rn.L);
+    const double aty = group_sum(seg_partial4<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
     if (rn.lane == 0) {
       red[0] += 0.5 * txj * px + q * txj;
       red[4] = fmax(red[4], fabs(d * (px + q + aty)));

@@ -111,11 +111,62 @@ __device__ __forceinline__ A seg_partial(const int *ci, const V *v, int b, int e
   return (s0 + s1) + (s2 + s3);
 }
 
+// Four consecutive entries from a 16-byte-aligned address.
+__device__ __forceinline__ void ld4(const int *p, int (&o)[4]) {
+  const int4 t = *reinterpret_cast<const int4 *>(p);
+  o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+}
+__device__ __forceinline__ void ld4(const float *p, float (&o)[4]) {
+  const float4 t = *reinterpret_cast<const float4 *>(p);
+  o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double (&o)[4]) {
+  const double2 t0 = *reinterpret_cast<const double2 *>(p);
+  const double2 t1 = *reinterpret_cast<const double2 *>(p + 2);
+  o[0] = t0.x; o[1] = t0.y; o[2] = t1.x; o[3] = t1.y;
+}
+
+// seg_partial with 16-byte loads: each lane takes aligned chunks of four
+// consecutive entries (the entry arrays of a QP start on a multiple of 4 and
+// are padded to one), four chunks per round.  Entries of a chunk outside
+// [b, e) are masked; a chunk past the row's end re-reads the row's last
+// chunk, which is in range, so every load is unconditional.
+template <class A, class V, class X>
+__device__ __forceinline__ A seg_partial4(const int *ci, const V *v, int b, int e, int lane,
+                                          int L, const X *x) {
+  A s0 = A(0), s1 = A(0), s2 = A(0), s3 = A(0);
+  if (e <= b) return A(0);
+  const int last = (e - 1) & ~3;
+  for (int k = (b & ~3) + 4 * lane; k < e; k += 16 * L) {
+    int c[4][4];
+    V a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = min(k + 4 * L * u, last);
+      ld4(ci + kk, c[u]);
+      ld4(v + kk, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * L * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = kk + q >= b && kk + q < e;
+        const int cq = ok ? c[u][q] : 0;
+        const A aq = ok ? A(a[u][q]) : A(0);
+        const A t = aq * A(x[cq]);
+        if (q == 0) s0 += t; else if (q == 1) s1 += t; else if (q == 2) s2 += t; else s3 += t;
+      }
+    }
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
 // The same for CSR row r.
 template <class A, class V, class X>
 __device__ __forceinline__ A row_partial(const int *rp, const int *ci, const V *v, int r,
                                          int lane, int L, const X *x) {
-  return seg_partial<A>(ci, v, rp[r], rp[r + 1], lane, L, x);
+  return seg_partial4<A>(ci, v, rp[r], rp[r + 1], lane, L, x);
 }
 
 // Rows j = g, g + ng, ... < cnt of one CSR (rp) or of two with the same row
@@ -459,7 +510,7 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
         const int in = rn2 < R ? v.mrows[rn2] : 0;
         const int bn = rn2 < R ? v.arp[in] : 0, en = rn2 < R ? v.arp[in + 1] : 0;
         const double sr = sqrt(rho_i(i));
-        const double a = group_sum(seg_partial<double>(v.aci, v.av, b, e, rm.lane, rm.L, u), rm.L);
+        const double a = group_sum(seg_partial4<double>(v.aci, v.av, b, e, rm.lane, rm.L, u), rm.L);
         if (rm.lane == 0) wc[r] = sr * a;
         r = rn2; i = in; b = bn; e = en;
       }
@@ -476,7 +527,7 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
     const Rows rn(tm, v.ln);
     rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
       const double uj = u[j], dj = dinv[j];
-      const double a = group_sum(seg_partial<double>(v.atci, v.atv, b, e, rn.lane, rn.L, wr), rn.L);
+      const double a = group_sum(seg_partial4<double>(v.atci, v.atv, b, e, rn.lane, rn.L, wr), rn.L);
       if (rn.lane == 0) {
         const double step = uj - dj * a;
         if (to_xt) v.xt[j] += step;
@@ -560,7 +611,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     for (int i = tm.tid; i < m; i += tm.nt) v.y[i] = c * v.Einv[i] * v.yws[i];
     tm.sync();
     for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
-      const double a = group_sum(seg_partial<double>(v.aci, v.av, b, e, lane, L, v.x), L);
+      const double a = group_sum(seg_partial4<double>(v.aci, v.av, b, e, lane, L, v.x), L);
       if (lane == 0) v.z[i] = a;
     });
   } else {
@@ -571,7 +622,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   // both in double from the double copy of A (a mixed-precision refinement:
   // each linear solve starts from a residual computed in FP64)
   for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
-    const double a = group_sum(seg_partial<double>(v.aci, v.av, b, e, lane, L, v.xt), L);
+    const double a = group_sum(seg_partial4<double>(v.aci, v.av, b, e, lane, L, v.xt), L);
     if (lane == 0) {
       v.zt64[i] = a;
       if (sizeof(T) == 4) v.zt[i] = T(a);
@@ -616,8 +667,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         // the row's own values are loaded before the gathers (they do not
         // depend on them), so their latency overlaps
         const double xj = v.x[j], xtj = v.xt[j], qj = v.q64[j];
-        double a = seg_partial<double>(v.atci, v.atv, ab, ae, rn.lane, rn.L, s_src) -
-                   seg_partial<double>(v.pci, v.pv, pb, pe, rn.lane, rn.L, x_src);
+        double a = seg_partial4<double>(v.atci, v.atv, ab, ae, rn.lane, rn.L, s_src) -
+                   seg_partial4<double>(v.pci, v.pv, pb, pe, rn.lane, rn.L, x_src);
         a = group_sum(a, rn.L);
         if (rn.lane == 0) {
           const double r64 = set.sigma * (xj - xtj) - qj + a;
@@ -677,7 +728,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       auto kprod = [&](const T *p_src, T *t_dst, const T *t_src) __attribute__((always_inline)) {
         for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
           const T ri = v.rho[i];
-          const T a = group_sum(seg_partial<T>(v.aci, v.av, b, e, lane, L, p_src), L);
+          const T a = group_sum(seg_partial4<T>(v.aci, v.av, b, e, lane, L, p_src), L);
           if (lane == 0) t_dst[i] = ri * a;
         });
         tm.sync();
@@ -685,8 +736,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
                     [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
           const T pj = v.p[j];
-          T a = seg_partial<T>(v.pci, v.pv, pb, pe, rn.lane, rn.L, p_src) +
-                seg_partial<T>(v.atci, v.atv, ab, ae, rn.lane, rn.L, t_src);
+          T a = seg_partial4<T>(v.pci, v.pv, pb, pe, rn.lane, rn.L, p_src) +
+                seg_partial4<T>(v.atci, v.atv, ab, ae, rn.lane, rn.L, t_src);
           a = group_sum(a, rn.L);
           if (rn.lane == 0) {
             const T wj = a + sigma * pj;
@@ -761,7 +812,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     auto upd_pass = [&](const double *xt_src) __attribute__((always_inline)) {
       for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
         const double zi = v.z[i], yi = v.y[i], ri = rho_of(i);
-        const double a64 = group_sum(seg_partial<double>(v.aci, v.av, b, e, lane, L, xt_src), L);
+        const double a64 = group_sum(seg_partial4<double>(v.aci, v.av, b, e, lane, L, xt_src), L);
         if (lane == 0) {
           const double vv = set.alpha * a64 + (1.0 - set.alpha) * zi + yi / ri;
           const double zn = fmin(fmax(vv, v.l64[i]), v.u64[i]);
