@@ -155,14 +155,15 @@ __device__ __forceinline__ void dense_syrk_tn(const WGTeam &tm, DenseLDS<T> &s, 
 }
 
 // S (R x R, lower triangle written) = G G' for G dense R x K, row-major
-// (ldg), FP64 on the vector ALUs.  64 x 64 output tiles from 32-wide k
-// panels staged in LDS; 256 virtual threads own a 4 x 4 block of a tile each
-// (rows ti + 16a, columns tj + 16c), so per k step a thread reads eight LDS
-// values for sixteen FMAs.  Workgroups of fewer than 256 threads take several
-// passes over a tile.
+// (ldg), FP64 on the vector ALUs.  64 x 64 output tiles from 64-wide k
+// panels staged in LDS (the triangular-solve block area); 256 virtual
+// threads own a 4 x 4 block of a tile each (rows ti + 16a, columns
+// tj + 16c), so per k step a thread reads eight LDS values for sixteen FMAs.
+// Workgroups of fewer than 256 threads take several passes over a tile.
 __device__ __forceinline__ void dense_gram_lower(const WGTeam &tm, DenseLDS<double> &s,
                                                  const double *G, int ldg, int R, int K,
                                                  double *S, int ldS) {
+  constexpr int KC = 64;
   const int passes = tm.nt >= 256 ? 1 : (256 + tm.nt - 1) / tm.nt;
   for (int i0 = 0; i0 < R; i0 += kTS) {
     const int ni = min(kTS, R - i0);
@@ -177,23 +178,23 @@ __device__ __forceinline__ void dense_gram_lower(const WGTeam &tm, DenseLDS<doub
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-        for (int k0 = 0; k0 < K; k0 += kNB) {
-          const int kd = min(kNB, K - k0);
+        for (int k0 = 0; k0 < K; k0 += KC) {
+          const int kd = min(KC, K - k0);
           tm.sync();
-          for (int e = tm.tid; e < kTS * kNB; e += tm.nt) {
-            const int r = e / kNB, t = e % kNB;
-            s.pa[r][t] = (r < ni && t < kd) ? G[(size_t)(i0 + r) * ldg + k0 + t] : 0.0;
-            s.pb[r][t] = (r < nj && t < kd) ? G[(size_t)(j0 + r) * ldg + k0 + t] : 0.0;
+          for (int e = tm.tid; e < kTS * KC; e += tm.nt) {
+            const int r = e / KC, t = e % KC;
+            s.blk[r][t] = (r < ni && t < kd) ? G[(size_t)(i0 + r) * ldg + k0 + t] : 0.0;
+            s.xs[r][t] = (r < nj && t < kd) ? G[(size_t)(j0 + r) * ldg + k0 + t] : 0.0;
           }
           tm.sync();
           if (act) {
 #pragma unroll 4
-            for (int t = 0; t < kNB; ++t) {
+            for (int t = 0; t < KC; ++t) {
               double av[4], bv[4];
 #pragma unroll
-              for (int a = 0; a < 4; ++a) av[a] = s.pa[ti + 16 * a][t];
+              for (int a = 0; a < 4; ++a) av[a] = s.blk[ti + 16 * a][t];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) bv[c] = s.pb[tj + 16 * c][t];
+              for (int c = 0; c < 4; ++c) bv[c] = s.xs[tj + 16 * c][t];
 #pragma unroll
               for (int a = 0; a < 4; ++a)
 #pragma unroll

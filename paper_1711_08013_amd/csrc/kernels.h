@@ -32,11 +32,12 @@ template <class T>
 __global__ void __launch_bounds__(kMaxBlock) scale_wg_kernel(Batch<T> b, const int *list,
                                                              int nlist, int slot) {
   __shared__ double red[(kMaxBlock / kWave) * kRedSlots];
+  __shared__ double stage[kStage];
   WGTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   __shared__ int slot_val;
   wg_queue(b.counter + slot, nlist, slot_val, [&](int qi) __attribute__((always_inline)) {
     QPView<T> v(b, list[qi]);
-    scale_qp<T>(tm, v, b.set);
+    scale_qp<T>(tm, v, b.set, stage);
   });
 }
 

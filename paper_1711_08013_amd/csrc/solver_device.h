@@ -162,6 +162,37 @@ __device__ __forceinline__ A seg_partial4(const int *ci, const V *v, int b, int 
   return (s0 + s1) + (s2 + s3);
 }
 
+// max_k |v[k]| s[ci[k]] over [b, e) for the lanes of a group (not reduced),
+// with the chunked unconditional loads of seg_chunks.
+template <class S>
+__device__ __forceinline__ double seg_absmax4(const int *ci, const double *v, int b, int e, int lane,
+                                              int L, const S *sc) {
+  double m0 = 0.0, m1 = 0.0;
+  if (e <= b) return 0.0;
+  const int last = (e - 1) & ~3;
+  for (int k = (b & ~3) + 4 * lane; k < e; k += 16 * L) {
+    int c[4][4];
+    double a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = min(k + 4 * L * u, last);
+      ld4(ci + kk, c[u]);
+      ld4(v + kk, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * L * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = kk + q >= b && kk + q < e;
+        const double t = ok ? fabs(a[u][q]) * double(sc[ok ? c[u][q] : 0]) : 0.0;
+        if (q & 1) m1 = fmax(m1, t); else m0 = fmax(m0, t);
+      }
+    }
+  }
+  return fmax(m0, m1);
+}
+
 // The same for CSR row r.
 template <class A, class V, class X>
 __device__ __forceinline__ A row_partial(const int *rp, const int *ci, const V *v, int r,
@@ -240,53 +271,65 @@ __device__ __forceinline__ double scale_a(double raw, double Ei, double Dj) {
 // resident unscaled data; then writes the scaled data in T and in double.
 // ------------------------------------------------------------------------
 template <class T, class Team>
-__device__ __forceinline__ void scale_qp(const Team &tm, const QPView<T> &v, const DevSettings &set) {
+__device__ __forceinline__ void scale_qp(const Team &tm, const QPView<T> &v, const DevSettings &set,
+                                         double *stage = nullptr) {
   const int n = v.n, m = v.m;
-  for (int j = tm.tid; j < n; j += tm.nt) v.D[j] = 1.0;
-  for (int i = tm.tid; i < m; i += tm.nt) v.E[i] = 1.0;
+  // D and E live in LDS during the passes when they fit (the norms gather
+  // from them), in global memory otherwise
+  const int n8 = (n + 7) & ~7;
+  const bool stg = stage != nullptr && n8 + ((m + 7) & ~7) <= kStage;
+  double *Dv = stg ? stage : v.D, *Ev = stg ? stage + n8 : v.E;
+  for (int j = tm.tid; j < n; j += tm.nt) Dv[j] = 1.0;
+  for (int i = tm.tid; i < m; i += tm.nt) Ev[i] = 1.0;
   double c = 1.0;
   tm.sync();
   const Rows rn(tm, v.ln), rm(tm, v.lm);
-  for (int it = 0; it < set.scaling_iters; ++it) {
-    // column infinity norms of M = [P A'; A 0] (current scaling) -> delta
-    for (int j = rn.g; j < n; j += rn.ng) {
-      double a = 0.0;
-      for (int k = v.prp[j] + rn.lane; k < v.prp[j + 1]; k += rn.L)
-        a = fmax(a, fabs(v.praw[k]) * v.D[v.pci[k]]);
-      a *= c;
-      for (int k = v.atrp[j] + rn.lane; k < v.atrp[j + 1]; k += rn.L)
-        a = fmax(a, fabs(v.atraw[k]) * v.E[v.atci[k]]);
-      a = group_max(a, rn.L) * v.D[j];
-      if (rn.lane == 0) v.dx[j] = 1.0 / sqrt(clamp_norm(a));
+  auto passes = [&](double *Ds, double *Es) __attribute__((always_inline)) {
+    for (int it = 0; it < set.scaling_iters; ++it) {
+      // column infinity norms of M = [P A'; A 0] (current scaling) -> delta
+      rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
+                  [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
+        const double Dj = Ds[j];
+        double a = c * seg_absmax4(v.pci, v.praw, pb, pe, rn.lane, rn.L, Ds);
+        a = fmax(a, seg_absmax4(v.atci, v.atraw, ab, ae, rn.lane, rn.L, Es));
+        a = group_max(a, rn.L) * Dj;
+        if (rn.lane == 0) v.dx[j] = 1.0 / sqrt(clamp_norm(a));
+      });
+      for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
+        const double Ei = Es[i];
+        double a = seg_absmax4(v.aci, v.araw, b, e, lane, L, Ds);
+        a = group_max(a, L) * Ei;
+        if (lane == 0) v.dy[i] = 1.0 / sqrt(clamp_norm(a));
+      });
+      tm.sync();
+      for (int j = tm.tid; j < n; j += tm.nt) Ds[j] *= v.dx[j];
+      for (int i = tm.tid; i < m; i += tm.nt) Es[i] *= v.dy[i];
+      tm.sync();
+      // cost scaling: gamma = 1 / max(mean_j ||Pbar_j||_inf, ||qbar||_inf)
+      double red[2] = {0.0, 0.0};
+      rows_ahead(v.prp, rn.g, rn.ng, n, [&](int j, int pb, int pe) __attribute__((always_inline)) {
+        const double Dj = Ds[j], qj = v.qraw[j];
+        double a = seg_absmax4(v.pci, v.praw, pb, pe, rn.lane, rn.L, Ds);
+        a = group_max(a, rn.L) * (c * Dj);
+        if (rn.lane == 0) {
+          red[0] += a;
+          red[1] = fmax(red[1], fabs(c * Dj * qj));
+        }
+      });
+      tm.template reduce<1, 1>(red);
+      const double s = fmax(red[0] / (double)n, red[1]);
+      // reading: gamma = 1 when P and q vanish, else clamped to [1e-4, 1e4]
+      const double gamma = s == 0.0 ? 1.0 : fmin(fmax(1.0 / s, 1e-4), 1e4);
+      c *= gamma;
     }
-    for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
-      double a = 0.0;
-      for (int k = b + lane; k < e; k += L)
-        a = fmax(a, fabs(v.araw[k]) * v.D[v.aci[k]]);
-      a = group_max(a, L) * v.E[i];
-      if (lane == 0) v.dy[i] = 1.0 / sqrt(clamp_norm(a));
-    });
+  };
+  if (stg) {
+    passes(stage, stage + n8);
+    for (int j = tm.tid; j < n; j += tm.nt) v.D[j] = stage[j];
+    for (int i = tm.tid; i < m; i += tm.nt) v.E[i] = stage[n8 + i];
     tm.sync();
-    for (int j = tm.tid; j < n; j += tm.nt) v.D[j] *= v.dx[j];
-    for (int i = tm.tid; i < m; i += tm.nt) v.E[i] *= v.dy[i];
-    tm.sync();
-    // cost scaling: gamma = 1 / max(mean_j ||Pbar_j||_inf, ||qbar||_inf)
-    double red[2] = {0.0, 0.0};
-    for (int j = rn.g; j < n; j += rn.ng) {
-      double a = 0.0;
-      for (int k = v.prp[j] + rn.lane; k < v.prp[j + 1]; k += rn.L)
-        a = fmax(a, fabs(v.praw[k]) * v.D[v.pci[k]]);
-      a = group_max(a, rn.L) * (c * v.D[j]);
-      if (rn.lane == 0) {
-        red[0] += a;
-        red[1] = fmax(red[1], fabs(c * v.D[j] * v.qraw[j]));
-      }
-    }
-    tm.template reduce<1, 1>(red);
-    const double s = fmax(red[0] / (double)n, red[1]);
-    // reading: gamma = 1 when P and q vanish, else clamped to [1e-4, 1e4]
-    const double gamma = s == 0.0 ? 1.0 : fmin(fmax(1.0 / s, 1e-4), 1e4);
-    c *= gamma;
+  } else {
+    passes(v.D, v.E);
   }
   // write the scaled problem: Pbar = c D P D, qbar = c D q, Abar = E A D,
   // lbar = E l, ubar = E u
