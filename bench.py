@@ -45,23 +45,25 @@ def build_workload(name: str, count: int | None):
 
 
 def algorithmic_bytes(qps, infos, value_bytes=4, check_every=25):
-    """Bytes the solve kernel must move, summed over the batch, counting each
-    matrix once per application at the width the path uses (index 4 B, FP64
-    value 8 B, working-precision value `value_bytes`) and each vector once per
-    pass.  Per QP with a = nnz(A), p = nnz(P full), a_m = entries of the rows
-    of A with several entries (R of them), n, m:
-      ADMM iteration (FP64): start pass A', P -> 12 (a + p) + 4 (2n) + 8 (5n + m);
-                             update pass A    -> 12 a + 4 m + 8 (3n + 9m)
-      PCG iteration (T)    : A, A', P -> (4 + vb)(2a + p) + 4 (2n + m) + vb (5n + 2m) + 16 n
-      preconditioner apply : low-rank -> 12 (a_m + a) + 8 (R^2 + 3n + 2m);
-                             dense    -> vb n^2 (two triangular sweeps) + vb 2n;
-                             Jacobi   -> in the PCG vectors
-        (applies = ADMM iterations + inner PCG iterations beyond the first)
-      check (FP64, every 25): 12 (2a + p) + 8 (6n + 6m)
-      factorisation (1 + rho updates): low-rank -> 8 (2 R n + R^2);
-                                       dense    -> vb (3 n^2)
+    """Bytes the solve kernel must move, summed over the batch: each matrix
+    once per application, at the width the path reads it (index 4 B + value
+    vb = `value_bytes` in the ADMM passes, FP64 8 B in the checks), each
+    vector once per pass.  Per QP with a = nnz(A), p = nnz(P full), a_m the
+    entries of the R rows of A with several entries, e = 4 + vb:
+      ADMM iteration : start pass A', P -> e (a + p) + 8 (6n + m);
+                       update pass A    -> e a + 8 (3n + 9m)
+      low-rank path  : one direct apply per iteration (counted in pcg_iter)
+                       -> e (a_m + a) + 8 (R^2 + 4n + 2m); no PCG products
+      dense path     : PCG iterations e (2a + p) + 4 (2n + m) + vb (5n + 2m) + 16n,
+                       applies (ADMM iterations + inner iterations beyond the
+                       first) vb n^2 + 2 vb n
+      Jacobi path    : PCG iterations as above, no applies
+      check (FP64, every 25 iterations): 12 (2a + p) + 8 (6n + 6m)
+      factorisation (1 + rho updates): low-rank 8 (2 R n + R^2) + e a_m;
+                                       dense 3 vb n^2
     """
     vb = value_bytes
+    e = 4 + vb
     total = 0.0
     for qp, info in zip(qps, infos):
         n, m = qp.n, qp.m
@@ -71,21 +73,21 @@ def algorithmic_bytes(qps, infos, value_bytes=4, check_every=25):
         am = int(rl[rl >= 2].sum())
         R = int((rl >= 2).sum())
         it, pcg = info["iter"], info["pcg_iter"]
-        admm = it * (12 * (a + p) + 8 * n + 8 * (5 * n + m) + 12 * a + 4 * m + 8 * (3 * n + 9 * m))
-        inner = pcg * ((4 + vb) * (2 * a + p) + 4 * (2 * n + m) + vb * (5 * n + 2 * m) + 16 * n)
-        applies = it + max(0, pcg - it)
+        admm = it * (e * (a + p) + 8 * (6 * n + m) + e * a + 8 * (3 * n + 9 * m))
+        pcg_b = e * (2 * a + p) + 4 * (2 * n + m) + vb * (5 * n + 2 * m) + 16 * n
         path = info.get("linsys", 1)
         if path == 3:
-            apply_b = 12 * (am + a) + 8 * (R * R + 3 * n + 2 * m)
-            fact_b = 8 * (2 * R * n + R * R)
+            work = pcg * (e * (am + a) + 8 * (R * R + 4 * n + 2 * m))
+            fact_b = 8 * (2 * R * n + R * R) + e * am
         elif path == 2:
-            apply_b = vb * n * n + vb * 2 * n
-            fact_b = vb * 3 * n * n
+            work = pcg * pcg_b + (it + max(0, pcg - it)) * (vb * n * n + 2 * vb * n)
+            fact_b = 3 * vb * n * n
         else:
-            apply_b, fact_b = 0, 0
+            work = pcg * pcg_b
+            fact_b = 0
         checks = -(-it // check_every)
         chk = checks * (12 * (2 * a + p) + 8 * (6 * n + 6 * m))
-        total += admm + inner + applies * apply_b + chk + (1 + info["rho_updates"]) * fact_b
+        total += admm + work + chk + (1 + info["rho_updates"]) * fact_b
     return float(total)
 
 
@@ -164,6 +166,50 @@ def fp64_plain(pm, qps, budget_s: float, extra: dict):
             "p99_latency_ms": float(np.percentile(times, 99) * 1e3)}
 
 
+def serving_leg(pm, n_req: int, rate: float, n_max_random: int, gen_budget_s: float):
+    """Continuous-batching server under a Poisson stream mixing the random-QP,
+    MPC and portfolio generators (repeats of an MPC plant or a portfolio
+    model share a structure key: resident data, update_vectors + warm
+    start).  Requests are generated first (bounded by gen_budget_s), then
+    submitted at their arrival times; latency is the server's own
+    submit-to-completion time."""
+    trace = qpgen.serving_trace(n_req, rate)
+    state, reqs = {}, []
+    t0 = time.perf_counter()
+    for r in trace:
+        qp = qpgen.serving_request(r, state, n_range=(20, n_max_random))
+        if r["key"] is None:
+            key = 0
+        else:
+            key = (1000 if r["key"][0] == "mpc" else 2000) + int(r["key"][1])
+        reqs.append((r["t"], qp, key))
+        if time.perf_counter() - t0 > gen_budget_s:
+            break
+    sv = pm.Server(hbm_budget_bytes=64 << 30, max_slots=1024, precision="fp32")
+    start = time.perf_counter()
+    tickets = []
+    for t_arr, qp, key in reqs:
+        delay = start + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(sv.submit(qp, key=key))
+    outs = [sv.wait(t) for t in tickets]
+    wall = time.perf_counter() - start
+    stats = sv.stats()
+    sv.close()
+    lat = np.array([o[3] for o in outs]) * 1e3
+    solved = sum(1 for o in outs if o[2]["status_name"] == "solved")
+    return {"requests": len(reqs), "offered_rate_qps": rate,
+            "arrival_span_s": round(reqs[-1][0], 3), "wall_s": round(wall, 3),
+            "throughput_qps": round(solved / wall, 1), "solved": solved,
+            "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
+            "mix": f"1/3 random QP (n log-uniform in [20, {n_max_random}], m = 10n), "
+                   "1/3 MPC (64 plants, repeats change x0), 1/3 portfolio (16 models, "
+                   "repeats change mu)",
+            "micro_batches": stats["batches"], "peak_inflight": stats["peak_inflight"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +220,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--fp64-budget", type=float, default=10.0)
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=600)
+    ap.add_argument("--serving-rate", type=float, default=2000.0)
+    ap.add_argument("--serving-nmax", type=int, default=1000,
+                    help="largest random-QP n in the serving mix")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -245,6 +296,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(qps, args.cpu_budget, extra)
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
     batch.close()
+    if not args.no_serving:
+        print("# serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(pm, args.serving_requests, args.serving_rate,
+                                     args.serving_nmax, gen_budget_s=30.0)
     print(json.dumps(out), flush=True)
 
 

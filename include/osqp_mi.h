@@ -186,6 +186,15 @@ osqp_int osqp_batch_solve(osqp_batch *b);
 /* Enqueue the solve on the batch's stream without waiting (results are
  * valid after osqp_batch_sync). */
 osqp_int osqp_batch_solve_async(osqp_batch *b);
+/* Enqueue the solve of the `count` QPs listed in idx (distinct indices into
+ * the batch, host memory, copied before return) without waiting; the other
+ * QPs keep their state.  Every listed QP runs on one workgroup (the
+ * whole-grid team is not used), with polishing when enabled and the QP is
+ * polishable.  This is how a resident set of structures is re-solved for the
+ * requests that arrived (Section 6: new vectors and warm starts, matrices and
+ * factors kept).  OSQP_ERR_INDEX for an index out of range or repeated;
+ * results after osqp_batch_sync. */
+osqp_int osqp_batch_solve_subset_async(osqp_batch *b, const osqp_int *idx, osqp_int count);
 osqp_int osqp_batch_sync(osqp_batch *b);
 /* Re-run the device-side Ruiz scaling from the resident unscaled data and
  * reset every iterate to zero (a fresh solve of the same problems). */
@@ -211,13 +220,17 @@ void osqp_batch_cleanup(osqp_batch *b);
 
 /* ---- continuous-batching server ----------------------------------------
  * A scheduler thread admits submitted QPs while slots (max_slots QPs on the
- * device at once) and the HBM budget allow.  QPs admitted together form a
- * micro-batch that is set up and solved on its own stream, so micro-batches
- * admitted while others run overlap on the device.  A nonzero
- * structure_key marks QPs that share matrices: the first one stays resident
- * (matrices, dense factor, iterates) and later ones reuse it through the
- * vector update and warm start of Section 6 (their P and A must equal the
- * first's; only q, l, u are taken).  Tickets are returned at submission.
+ * device at once), the HBM budget and a limit of launches in flight allow;
+ * while the device is full, requests accumulate and are admitted together
+ * when a launch drains.  Fresh QPs admitted together form a micro-batch set
+ * up and solved on its own stream, so launches admitted while others run
+ * overlap on the device.  A nonzero structure_key marks QPs that share
+ * matrices: first requests of new keys form a resident pool (matrices,
+ * scaling, factors, iterates stay on the device) and later requests of those
+ * keys are re-solved together as a subset of their pool through the vector
+ * update and warm start of Section 6 (their P and A must equal the first's;
+ * only q, l, u are taken).  Idle pools are evicted least recently used
+ * first when the budget needs room.  Tickets are returned at submission.
  * Calls from several client threads are allowed. */
 osqp_int osqp_server_create(osqp_server **out, size_t hbm_budget_bytes, osqp_int max_slots,
                             const osqp_settings *s);

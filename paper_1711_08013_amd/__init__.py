@@ -30,7 +30,8 @@ EXPORTS = [
     "osqp_device_info", "osqp_setup",
     "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_get_solution",
     "osqp_get_info", "osqp_cleanup", "osqp_batch_setup", "osqp_batch_solve",
-    "osqp_batch_solve_async", "osqp_batch_sync", "osqp_batch_reset",
+    "osqp_batch_solve_async", "osqp_batch_solve_subset_async", "osqp_batch_sync",
+    "osqp_batch_reset",
     "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_get",
     "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_get_factor",
     "osqp_batch_cleanup", "osqp_server_create", "osqp_server_submit", "osqp_server_wait",
@@ -202,6 +203,14 @@ class Batch:
 
     def solve_async(self):
         _check(lib().osqp_batch_solve_async(self._h), "osqp_batch_solve_async")
+
+    def solve_subset(self, indices):
+        """Solve only the listed QPs (the others keep their state)."""
+        idx = np.ascontiguousarray(indices, dtype=np.int32)
+        _check(lib().osqp_batch_solve_subset_async(
+            self._h, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(idx.size)),
+            "osqp_batch_solve_subset_async")
+        self.sync()
 
     def sync(self):
         _check(lib().osqp_batch_sync(self._h), "osqp_batch_sync")

@@ -139,6 +139,7 @@ struct osqp_batch {
   std::vector<int> mrows;
   // host staging of the inputs that change through the parametric API
   std::vector<double> q_raw, l_raw, u_raw;
+  std::vector<double> xws_h, yws_h;   // warm-start staging
   std::vector<unsigned char> is_eq;
   // device
   char *arena = nullptr;
@@ -146,6 +147,9 @@ struct osqp_batch {
   Batch<double> bd{};
   Batch<float> bf{};
   int *d_small = nullptr, *d_big = nullptr;
+  int *d_subset = nullptr, *d_subset_polish = nullptr;   // lists of a subset solve
+  std::vector<int> subset_h, subset_pol_h;              // their host staging
+  std::vector<char> polishable;                         // QP is in polish_list
   double *d_partials = nullptr;
   GridBarrier *d_bar = nullptr;
   int block = 256, grid_wg = 0, grid_coop = 0, coop_block = 256;
@@ -350,6 +354,40 @@ int launch_solve(osqp_batch *b) {
   return OSQP_OK;
 }
 
+// Solve of a subset of the batch's QPs, each on one workgroup.
+template <class T>
+int launch_subset(osqp_batch *b, const std::vector<int> &idx, const std::vector<int> &pol) {
+  Batch<T> &B = batch_of<T>(b);
+  B.set = b->dev_settings();
+  if (!b->d_subset) {
+    if (hipMalloc(&b->d_subset, sizeof(int) * b->nq) != hipSuccess ||
+        hipMalloc(&b->d_subset_polish, sizeof(int) * b->nq) != hipSuccess)
+      return OSQP_ERR_ALLOC;
+  }
+  // the lists are staged in the batch's own host buffers, which stay
+  // untouched until the next subset solve of this batch
+  b->subset_h = idx;
+  b->subset_pol_h = pol;
+  const int nl = (int)idx.size();
+  HIPCHK(hipMemcpyAsync(b->d_subset, b->subset_h.data(), sizeof(int) * nl, hipMemcpyHostToDevice,
+                        b->stream));
+  if (!pol.empty())
+    HIPCHK(hipMemcpyAsync(b->d_subset_polish, b->subset_pol_h.data(), sizeof(int) * pol.size(),
+                          hipMemcpyHostToDevice, b->stream));
+  reset_counters_kernel<<<1, 64, 0, b->stream>>>(B.counter, 64, nullptr);
+  HIPCHK(hipEventRecord(b->ev0, b->stream));
+  const int grid = std::max(1, std::min(nl, b->grid_wg));
+  solve_wg_kernel<T><<<grid, b->block, 0, b->stream>>>(B, b->d_subset, nl, 1);
+  HIPCHK(hipEventRecord(b->ev1, b->stream));
+  if (b->set.polish && !pol.empty()) {
+    const int np = (int)pol.size();
+    polish_wg_kernel<T><<<std::min(np, b->polish_slots), kPolishBlock, 0, b->stream>>>(
+        B, b->d_subset_polish, np, 2, b->d_pws, b->pws_stride, b->polish_rmax);
+  }
+  HIPCHK(hipGetLastError());
+  return OSQP_OK;
+}
+
 int fetch_results(osqp_batch *b) {
   const Batch<double> &B = b->bd;
   const QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
@@ -373,6 +411,8 @@ void destroy(osqp_batch *b) {
   if (b->d_pws) (void)hipFree(b->d_pws);
   if (b->d_polish) (void)hipFree(b->d_polish);
   if (b->d_small) (void)hipFree(b->d_small);
+  if (b->d_subset) (void)hipFree(b->d_subset);
+  if (b->d_subset_polish) (void)hipFree(b->d_subset_polish);
   if (b->d_big) (void)hipFree(b->d_big);
   if (b->d_partials) (void)hipFree(b->d_partials);
   if (b->d_bar) (void)hipFree(b->d_bar);
@@ -619,6 +659,7 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
   std::vector<int> a_ci(na), at_ci(na), p_ci(np);
   std::vector<double> a_raw(na), at_raw(na), p_raw(np);
   b->q_raw.resize(sn); b->l_raw.resize(sm); b->u_raw.resize(sm); b->is_eq.resize(sm);
+  b->xws_h.resize(sn); b->yws_h.resize(std::max<int64_t>(sm, 1));
   for (int k = 0; k < count; ++k) {
     const osqp_problem &p = probs[k];
     const QPDesc &d = b->desc[k];
@@ -735,12 +776,14 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
   // polishing workspace: QPs with the low-rank condensed form (P diagonal,
   // few multi-entry rows) and the others with n <= kPolishMaxN (dense
   // condensed system); larger ones are reported as "polish not run"
+  b->polishable.assign(count, 0);
   if (s.polish) {
     int rmax = 0;
     for (int k = 0; k < count; ++k) {
       const osqp_problem &p = probs[k];
       if (!b->desc[k].plr && p.n > kPolishMaxN) continue;
       b->polish_list.push_back(k);
+      b->polishable[k] = 1;
       rmax = std::max(rmax, b->desc[k].mr_cnt);
     }
     if (!b->polish_list.empty()) {
@@ -904,6 +947,23 @@ osqp_int osqp_batch_solve_async(osqp_batch *b) {
   }
 }
 
+osqp_int osqp_batch_solve_subset_async(osqp_batch *b, const osqp_int *idx, osqp_int count) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (count <= 0 || !idx) return OSQP_ERR_DIM;
+  std::vector<int> list(idx, idx + count), pol;
+  std::vector<char> seen(b->nq, 0);
+  for (int k : list) {
+    if (k < 0 || k >= b->nq || seen[k]) return OSQP_ERR_INDEX;
+    seen[k] = 1;
+    if (b->polishable[k]) pol.push_back(k);
+  }
+  try {
+    return b->fp64 ? launch_subset<double>(b, list, pol) : launch_subset<float>(b, list, pol);
+  } catch (...) {
+    return OSQP_ERR_DEVICE;
+  }
+}
+
 osqp_int osqp_batch_sync(osqp_batch *b) {
   if (!b) return OSQP_ERR_NOT_SETUP;
   int rc = fetch_results(b);
@@ -951,8 +1011,16 @@ osqp_int osqp_batch_reset(osqp_batch *b) {
   return OSQP_OK;
 }
 
-osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *q,
-                                   const osqp_float *l, const osqp_float *u) {
+}  // extern "C"
+
+namespace {
+
+// The vector update of Section 6 on the batch's stream.  With sync = false
+// the call returns once the work is queued: the caller keeps the batch's
+// host staging untouched (no other update of this batch) until the stream
+// has drained (the server serialises the requests of one structure).
+int update_vectors_impl(osqp_batch *b, int i, const double *q, const double *l, const double *u,
+                        bool sync) {
   if (!b) return OSQP_ERR_NOT_SETUP;
   if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
   const QPDesc &d = b->desc[i];
@@ -1000,8 +1068,46 @@ osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *
   else
     rescale_vectors_wg_kernel<float><<<1, 256, 0, b->stream>>>(b->bf, i);
   if (hipGetLastError() != hipSuccess) return OSQP_ERR_DEVICE;
-  if (hipStreamSynchronize(b->stream) != hipSuccess) return OSQP_ERR_DEVICE;
+  if (sync && hipStreamSynchronize(b->stream) != hipSuccess) return OSQP_ERR_DEVICE;
   return OSQP_OK;
+}
+
+// Warm start of Section 6 on the batch's stream; the values are staged in
+// the batch's own host buffers (sync = false: as for update_vectors_impl).
+int warm_start_impl(osqp_batch *b, int i, const double *x, const double *y, bool sync) {
+  static const int kModeWarm = 2;
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
+  const QPDesc &d = b->desc[i];
+  // NULL keeps the current iterate: take it from the last solution
+  double *xs = &b->xws_h[d.xo], *ys = b->yws_h.data() + d.yo;
+  for (int j = 0; j < d.n; ++j)
+    if (!std::isfinite(x ? x[j] : b->xo[d.xo + j])) return OSQP_ERR_DATA_NONFINITE;
+  for (int k = 0; k < d.m; ++k)
+    if (!std::isfinite(y ? y[k] : b->yo[d.yo + k])) return OSQP_ERR_DATA_NONFINITE;
+  std::memcpy(xs, x ? x : &b->xo[d.xo], sizeof(double) * d.n);
+  if (d.m) std::memcpy(ys, y ? y : &b->yo[d.yo], sizeof(double) * d.m);
+  auto push = [&](auto &B) -> int {
+    HIPCHK(hipMemcpyAsync((void *)(B.xws + d.xo), xs, sizeof(double) * d.n,
+                          hipMemcpyHostToDevice, b->stream));
+    if (d.m)
+      HIPCHK(hipMemcpyAsync((void *)(B.yws + d.yo), ys, sizeof(double) * d.m,
+                            hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync((void *)&B.st[i].init_mode, &kModeWarm, sizeof(int),
+                          hipMemcpyHostToDevice, b->stream));
+    if (sync) HIPCHK(hipStreamSynchronize(b->stream));
+    return OSQP_OK;
+  };
+  return b->fp64 ? push(b->bd) : push(b->bf);
+}
+
+}  // namespace
+
+extern "C" {
+
+osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *q,
+                                   const osqp_float *l, const osqp_float *u) {
+  return update_vectors_impl(b, i, q, l, u, true);
 }
 
 osqp_int osqp_update_vectors(osqp_solver *h, const osqp_float *q, const osqp_float *l,
@@ -1011,32 +1117,7 @@ osqp_int osqp_update_vectors(osqp_solver *h, const osqp_float *q, const osqp_flo
 
 osqp_int osqp_batch_warm_start(osqp_batch *b, osqp_int i, const osqp_float *x,
                                const osqp_float *y) {
-  if (!b) return OSQP_ERR_NOT_SETUP;
-  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
-  const QPDesc &d = b->desc[i];
-  // NULL keeps the current iterate: take it from the last solution
-  std::vector<double> xs(d.n), ys(d.m);
-  if (x) std::memcpy(xs.data(), x, sizeof(double) * d.n);
-  else std::memcpy(xs.data(), &b->xo[d.xo], sizeof(double) * d.n);
-  if (y) std::memcpy(ys.data(), y, sizeof(double) * d.m);
-  else if (d.m) std::memcpy(ys.data(), &b->yo[d.yo], sizeof(double) * d.m);
-  for (double v : xs)
-    if (!std::isfinite(v)) return OSQP_ERR_DATA_NONFINITE;
-  for (double v : ys)
-    if (!std::isfinite(v)) return OSQP_ERR_DATA_NONFINITE;
-  auto push = [&](auto &B) -> int {
-    HIPCHK(hipMemcpyAsync((void *)(B.xws + d.xo), xs.data(), sizeof(double) * d.n,
-                          hipMemcpyHostToDevice, b->stream));
-    if (d.m)
-      HIPCHK(hipMemcpyAsync((void *)(B.yws + d.yo), ys.data(), sizeof(double) * d.m,
-                            hipMemcpyHostToDevice, b->stream));
-    const int mode = 2;
-    HIPCHK(hipMemcpyAsync((void *)&B.st[i].init_mode, &mode, sizeof(int), hipMemcpyHostToDevice,
-                          b->stream));
-    HIPCHK(hipStreamSynchronize(b->stream));
-    return OSQP_OK;
-  };
-  return b->fp64 ? push(b->bd) : push(b->bf);
+  return warm_start_impl(b, i, x, y, true);
 }
 
 osqp_int osqp_warm_start(osqp_solver *h, const osqp_float *x, const osqp_float *y) {

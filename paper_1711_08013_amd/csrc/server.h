@@ -2,12 +2,13 @@
 // Included at the end of api.hip: it drives the batch API above.
 //
 // One scheduler thread owns the device work.  Each pass it (1) retires
-// micro-batches whose stream has drained and hands their results to the
-// waiting clients, (2) admits queued requests while slots and the HBM budget
-// allow -- fresh QPs are grouped into one new micro-batch, a QP whose
-// structure key is resident is re-solved in place through the vector update
-// and warm start of Section 6 -- and launches them asynchronously on their
-// own streams, so work admitted now overlaps work already on the device.
+// launches whose stream has drained and hands their results to the waiting
+// clients, (2) admits queued requests while slots, the HBM budget and the
+// launch limit allow: fresh QPs form one new micro-batch, first requests of
+// new structure keys one new resident pool, and requests for keys already
+// resident one subset re-solve per pool through the vector update and warm
+// start of Section 6 -- each launched asynchronously on its batch's stream,
+// so work admitted now overlaps work already on the device.
 #pragma once
 
 #include <atomic>
@@ -19,6 +20,8 @@
 #include <unordered_map>
 
 namespace {
+
+constexpr int kServerMaxLaunches = 8;   // launches on the device at once
 
 struct OwnedQP {
   int n = 0, m = 0;
@@ -69,19 +72,30 @@ struct ServerResult {
   double latency = 0.0;
 };
 
-struct Resident {
+// A resident batch holding the structures of several keys: matrices,
+// scaling, factors and iterates stay on the device; requests for its keys
+// are re-solved as a subset of it (new vectors, warm start from the last
+// solution of the same key).
+struct Pool {
   osqp_batch *b = nullptr;
+  std::vector<uint64_t> keys;   // key of each QP of the batch
   size_t bytes = 0;
-  bool busy = false;
+  bool busy = false;            // a solve of this batch is on the device
   uint64_t last_use = 0;
 };
 
+struct KeySlot {
+  int pool = -1, idx = -1;
+};
+
+// kind: 0 fresh micro-batch, 1 new pool (first requests of new keys),
+// 2 re-solve of a subset of a pool
 struct InFlight {
   osqp_batch *b = nullptr;
-  bool resident = false;
-  uint64_t key = 0;
+  int kind = 0, pool = -1;
   size_t bytes = 0;
   std::vector<std::shared_ptr<ServerReq>> reqs;
+  std::vector<int> idx;         // batch index of each request
 };
 
 // HBM a request needs on the device (arena, dense factor, polish workspace).
@@ -105,7 +119,10 @@ struct osqp_server {
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<ServerReq>> queue;
   std::unordered_map<uint64_t, ServerResult> results;
-  std::unordered_map<uint64_t, Resident> resident;
+  std::unordered_map<int, Pool> pools;
+  std::unordered_map<uint64_t, KeySlot> keymap;     // resident keys
+  std::unordered_map<uint64_t, int> pending_keys;   // keys of a new pool on the device
+  int next_pool = 1;
   std::vector<InFlight> inflight;
   size_t used = 0;
   int slots = 0;
@@ -124,26 +141,35 @@ void server_finish(osqp_server *sv, InFlight &f) {
   for (size_t k = 0; k < f.reqs.size(); ++k) {
     ServerResult &r = out[k];
     r.done = true;
-    r.rc = rc;
-    const int idx = f.resident ? 0 : (int)k;
     r.x.resize(f.reqs[k]->qp.n);
     r.y.resize(f.reqs[k]->qp.m);
-    if (rc == OSQP_OK)
-      rc = osqp_batch_get(f.b, idx, r.x.data(), r.y.data(), &r.info);
-    r.rc = rc;
+    int rk = rc;
+    if (rk == OSQP_OK) rk = osqp_batch_get(f.b, f.idx[k], r.x.data(), r.y.data(), &r.info);
+    r.rc = rk;
     r.latency = now - f.reqs[k]->t_submit;
   }
   std::lock_guard<std::mutex> g(sv->mu);
   for (size_t k = 0; k < f.reqs.size(); ++k) sv->results[f.reqs[k]->ticket] = std::move(out[k]);
   sv->completed += (int64_t)f.reqs.size();
   sv->slots -= (int)f.reqs.size();
-  if (f.resident) {
-    Resident &r = sv->resident[f.key];
-    r.busy = false;
-    r.last_use = ++sv->tick;
-  } else {
+  if (f.kind == 0) {
     osqp_batch_cleanup(f.b);
     sv->used -= f.bytes;
+  } else if (f.kind == 1) {
+    Pool pl;
+    pl.b = f.b;
+    pl.bytes = f.bytes;
+    pl.last_use = ++sv->tick;
+    for (size_t k = 0; k < f.reqs.size(); ++k) {
+      pl.keys.push_back(f.reqs[k]->key);
+      sv->keymap[f.reqs[k]->key] = KeySlot{f.pool, (int)k};
+      sv->pending_keys.erase(f.reqs[k]->key);
+    }
+    sv->pools[f.pool] = std::move(pl);
+  } else {
+    Pool &pl = sv->pools[f.pool];
+    pl.busy = false;
+    pl.last_use = ++sv->tick;
   }
   sv->cv_done.notify_all();
   sv->cv_work.notify_all();
@@ -157,6 +183,7 @@ void server_fail(osqp_server *sv, const std::vector<std::shared_ptr<ServerReq>> 
     r.done = true;
     r.rc = rc;
     sv->results[q->ticket] = std::move(r);
+    sv->pending_keys.erase(q->key);
   }
   sv->slots -= (int)reqs.size();
   sv->used -= bytes;
@@ -164,9 +191,47 @@ void server_fail(osqp_server *sv, const std::vector<std::shared_ptr<ServerReq>> 
   sv->cv_done.notify_all();
 }
 
+// Evict idle pools, least recently used first, until `need` more bytes fit
+// (called with the lock held).
+bool server_make_room(osqp_server *sv, size_t need) {
+  while (sv->used + need > sv->budget) {
+    int victim = 0;
+    uint64_t best = UINT64_MAX;
+    for (auto &kv : sv->pools)
+      if (!kv.second.busy && kv.second.last_use < best) { best = kv.second.last_use; victim = kv.first; }
+    if (!victim) return false;
+    Pool &pl = sv->pools[victim];
+    for (uint64_t key : pl.keys) sv->keymap.erase(key);
+    osqp_batch_cleanup(pl.b);
+    sv->used -= pl.bytes;
+    sv->pools.erase(victim);
+  }
+  return true;
+}
+
+// Setup (and warm starts) of a new batch from requests; solve queued.
+int server_new_batch(osqp_server *sv, const std::vector<std::shared_ptr<ServerReq>> &reqs,
+                     osqp_batch **out) {
+  std::vector<osqp_problem> probs;
+  for (auto &r : reqs) probs.push_back(r->qp.view());
+  osqp_batch *b = nullptr;
+  int rc = osqp_batch_setup(&b, (int)probs.size(), probs.data(), &sv->set);
+  for (size_t k = 0; rc == OSQP_OK && k < reqs.size(); ++k)
+    if (reqs[k]->qp.has_x || reqs[k]->qp.has_y)
+      rc = warm_start_impl(b, (int)k, reqs[k]->qp.has_x ? reqs[k]->qp.xws.data() : nullptr,
+                           reqs[k]->qp.has_y ? reqs[k]->qp.yws.data() : nullptr, false);
+  if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+  if (rc != OSQP_OK && b) {
+    osqp_batch_cleanup(b);
+    b = nullptr;
+  }
+  *out = b;
+  return rc;
+}
+
 void server_loop(osqp_server *sv) {
   for (;;) {
-    // (1) retire drained micro-batches
+    // (1) retire drained launches
     std::vector<InFlight> done;
     {
       std::lock_guard<std::mutex> g(sv->mu);
@@ -181,9 +246,17 @@ void server_loop(osqp_server *sv) {
     }
     for (auto &f : done) server_finish(sv, f);
 
-    // (2) admission under the lock, launches outside it
-    std::vector<std::shared_ptr<ServerReq>> fresh, repeats, firsts;
-    size_t fresh_bytes = 0;
+    // (2) admission under the lock, launches outside it.  At most
+    // kServerMaxLaunches launches are on the device at once; while it is
+    // full, requests accumulate and are admitted together when a launch
+    // drains (continuous batching: few large launches instead of many small
+    // ones queued on the device's few hardware queues).  Each round forms
+    // one micro-batch of fresh QPs, one new pool of first requests of new
+    // keys, and one subset re-solve per resident pool with requests.
+    std::vector<std::shared_ptr<ServerReq>> fresh, firsts;
+    std::unordered_map<int, std::vector<std::pair<std::shared_ptr<ServerReq>, int>>> repeats;
+    size_t fresh_bytes = 0, first_bytes = 0;
+    int new_pool = 0;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       if (sv->queue.empty() && sv->inflight.empty()) {
@@ -191,119 +264,113 @@ void server_loop(osqp_server *sv) {
         sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
         if (sv->stop && sv->queue.empty()) return;
       }
+      int launches = (int)sv->inflight.size();
+      std::unordered_map<uint64_t, int> chosen;
       for (auto it = sv->queue.begin(); it != sv->queue.end();) {
         auto &rq = *it;
-        if (sv->slots + (int)(fresh.size() + repeats.size() + firsts.size()) >= sv->max_slots) break;
-        if (rq->key) {
-          auto r = sv->resident.find(rq->key);
-          if (r != sv->resident.end()) {
-            bool pending = false;   // an earlier request of this key is admitted now
-            for (auto &x : repeats) pending |= x->key == rq->key;
-            for (auto &x : firsts) pending |= x->key == rq->key;
-            if (r->second.busy || pending) { ++it; continue; }
-            r->second.busy = true;
-            repeats.push_back(rq);
-            it = sv->queue.erase(it);
-            continue;
-          }
-          bool pending = false;
-          for (auto &x : firsts) pending |= x->key == rq->key;
-          if (pending) { ++it; continue; }
-          // make room by evicting idle resident structures, oldest first
-          while (sv->used + fresh_bytes + rq->bytes > sv->budget) {
-            uint64_t victim = 0, best = UINT64_MAX;
-            for (auto &kv : sv->resident)
-              if (!kv.second.busy && kv.second.last_use < best) { best = kv.second.last_use; victim = kv.first; }
-            if (!victim) break;
-            osqp_batch_cleanup(sv->resident[victim].b);
-            sv->used -= sv->resident[victim].bytes;
-            sv->resident.erase(victim);
-          }
-          if (sv->used + fresh_bytes + rq->bytes > sv->budget) break;
-          Resident nr;
-          nr.busy = true;
-          nr.bytes = rq->bytes;
-          sv->resident[rq->key] = nr;
-          sv->used += rq->bytes;
-          firsts.push_back(rq);
+        int admitted = (int)(fresh.size() + firsts.size());
+        for (auto &kv : repeats) admitted += (int)kv.second.size();
+        if (sv->slots + admitted >= sv->max_slots) break;
+        if (rq->key == 0) {
+          if (fresh.empty() && launches >= kServerMaxLaunches) break;   // FIFO for fresh QPs
+          if (!server_make_room(sv, fresh_bytes + first_bytes + rq->bytes)) break;
+          if (fresh.empty()) ++launches;
+          fresh_bytes += rq->bytes;
+          fresh.push_back(rq);
           it = sv->queue.erase(it);
           continue;
         }
-        if (sv->used + fresh_bytes + rq->bytes > sv->budget) break;
-        fresh_bytes += rq->bytes;
-        fresh.push_back(rq);
+        if (chosen.count(rq->key) || sv->pending_keys.count(rq->key)) { ++it; continue; }
+        auto ks = sv->keymap.find(rq->key);
+        if (ks != sv->keymap.end()) {
+          Pool &pl = sv->pools[ks->second.pool];
+          const bool opens = !repeats.count(ks->second.pool);
+          if (pl.busy || (opens && launches >= kServerMaxLaunches)) { ++it; continue; }
+          if (opens) ++launches;
+          repeats[ks->second.pool].push_back({rq, ks->second.idx});
+          chosen[rq->key] = 1;
+          it = sv->queue.erase(it);
+          continue;
+        }
+        // first request of a key: joins this round's new pool
+        if (firsts.empty() && launches >= kServerMaxLaunches) { ++it; continue; }
+        if (!server_make_room(sv, fresh_bytes + first_bytes + rq->bytes)) { ++it; continue; }
+        if (firsts.empty()) ++launches;
+        first_bytes += rq->bytes;
+        firsts.push_back(rq);
+        chosen[rq->key] = 1;
         it = sv->queue.erase(it);
       }
-      sv->used += fresh_bytes;
-      sv->slots += (int)(fresh.size() + repeats.size() + firsts.size());
+      for (auto &kv : repeats) sv->pools[kv.first].busy = true;
+      if (!firsts.empty()) {
+        new_pool = sv->next_pool++;
+        for (auto &r : firsts) sv->pending_keys[r->key] = new_pool;
+      }
+      sv->used += fresh_bytes + first_bytes;
+      int admitted = (int)(fresh.size() + firsts.size());
+      for (auto &kv : repeats) admitted += (int)kv.second.size();
+      sv->slots += admitted;
       sv->peak_bytes = std::max<int64_t>(sv->peak_bytes, (int64_t)sv->used);
     }
     std::vector<InFlight> launched;
     if (!fresh.empty()) {
-      std::vector<osqp_problem> probs;
-      for (auto &r : fresh) probs.push_back(r->qp.view());
       osqp_batch *b = nullptr;
-      int rc = osqp_batch_setup(&b, (int)probs.size(), probs.data(), &sv->set);
-      for (size_t k = 0; rc == OSQP_OK && k < fresh.size(); ++k)
-        if (fresh[k]->qp.has_x || fresh[k]->qp.has_y)
-          rc = osqp_batch_warm_start(b, (int)k, fresh[k]->qp.has_x ? fresh[k]->qp.xws.data() : nullptr,
-                                     fresh[k]->qp.has_y ? fresh[k]->qp.yws.data() : nullptr);
-      if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+      const int rc = server_new_batch(sv, fresh, &b);
       if (rc == OSQP_OK) {
         InFlight f;
-        f.b = b; f.bytes = fresh_bytes; f.reqs = fresh;
+        f.b = b; f.kind = 0; f.bytes = fresh_bytes; f.reqs = fresh;
+        for (size_t k = 0; k < fresh.size(); ++k) f.idx.push_back((int)k);
         launched.push_back(std::move(f));
       } else {
-        if (b) osqp_batch_cleanup(b);
         server_fail(sv, fresh, rc, fresh_bytes);
       }
     }
-    for (auto &rq : firsts) {
-      osqp_problem p = rq->qp.view();
+    if (!firsts.empty()) {
       osqp_batch *b = nullptr;
-      int rc = osqp_batch_setup(&b, 1, &p, &sv->set);
-      if (rc == OSQP_OK && (rq->qp.has_x || rq->qp.has_y))
-        rc = osqp_batch_warm_start(b, 0, rq->qp.has_x ? rq->qp.xws.data() : nullptr,
-                                   rq->qp.has_y ? rq->qp.yws.data() : nullptr);
-      if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+      const int rc = server_new_batch(sv, firsts, &b);
       if (rc == OSQP_OK) {
-        {
-          std::lock_guard<std::mutex> g(sv->mu);
-          sv->resident[rq->key].b = b;
-        }
         InFlight f;
-        f.b = b; f.resident = true; f.key = rq->key; f.reqs = {rq};
+        f.b = b; f.kind = 1; f.pool = new_pool; f.bytes = first_bytes; f.reqs = firsts;
+        for (size_t k = 0; k < firsts.size(); ++k) f.idx.push_back((int)k);
         launched.push_back(std::move(f));
       } else {
-        if (b) osqp_batch_cleanup(b);
-        {
-          std::lock_guard<std::mutex> g(sv->mu);
-          sv->resident.erase(rq->key);
-        }
-        server_fail(sv, {rq}, rc, rq->bytes);
+        server_fail(sv, firsts, rc, first_bytes);
       }
     }
-    for (auto &rq : repeats) {
+    for (auto &kv : repeats) {
       osqp_batch *b;
       {
         std::lock_guard<std::mutex> g(sv->mu);
-        b = sv->resident[rq->key].b;
+        b = sv->pools[kv.first].b;
       }
-      int rc = osqp_batch_update_vectors(b, 0, rq->qp.q.data(), rq->qp.l.data(), rq->qp.u.data());
-      if (rc == OSQP_OK && (rq->qp.has_x || rq->qp.has_y))
-        rc = osqp_batch_warm_start(b, 0, rq->qp.has_x ? rq->qp.xws.data() : nullptr,
-                                   rq->qp.has_y ? rq->qp.yws.data() : nullptr);
-      if (rc == OSQP_OK) rc = osqp_batch_solve_async(b);
+      // queued on the pool's stream without waiting: the requests keep their
+      // data and the pool stays busy until the solve has drained
+      int rc = OSQP_OK;
+      std::vector<osqp_int> idx;
+      std::vector<std::shared_ptr<ServerReq>> reqs;
+      for (auto &pr : kv.second) {
+        const auto &rq = pr.first;
+        if (rc == OSQP_OK)
+          rc = update_vectors_impl(b, pr.second, rq->qp.q.data(), rq->qp.l.data(), rq->qp.u.data(),
+                                   false);
+        if (rc == OSQP_OK && (rq->qp.has_x || rq->qp.has_y))
+          rc = warm_start_impl(b, pr.second, rq->qp.has_x ? rq->qp.xws.data() : nullptr,
+                               rq->qp.has_y ? rq->qp.yws.data() : nullptr, false);
+        idx.push_back(pr.second);
+        reqs.push_back(rq);
+      }
+      if (rc == OSQP_OK) rc = osqp_batch_solve_subset_async(b, idx.data(), (osqp_int)idx.size());
       if (rc == OSQP_OK) {
         InFlight f;
-        f.b = b; f.resident = true; f.key = rq->key; f.reqs = {rq};
+        f.b = b; f.kind = 2; f.pool = kv.first; f.reqs = reqs;
+        for (auto i : idx) f.idx.push_back(i);
         launched.push_back(std::move(f));
       } else {
         {
           std::lock_guard<std::mutex> g(sv->mu);
-          sv->resident[rq->key].busy = false;
+          sv->pools[kv.first].busy = false;
         }
-        server_fail(sv, {rq}, rc, 0);
+        server_fail(sv, reqs, rc, 0);
       }
     }
     {
@@ -410,9 +477,9 @@ void osqp_server_destroy(osqp_server *sv) {
   if (sv->worker.joinable()) sv->worker.join();
   for (auto &f : sv->inflight) {
     (void)osqp_batch_sync(f.b);
-    if (!f.resident) osqp_batch_cleanup(f.b);
+    if (f.kind != 2) osqp_batch_cleanup(f.b);   // pools are freed below
   }
-  for (auto &kv : sv->resident)
+  for (auto &kv : sv->pools)
     if (kv.second.b) osqp_batch_cleanup(kv.second.b);
   delete sv;
 }
