@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kMaxBlock) solve_wg_kernel(Batch<T> b, const i
 
 // FP64 polishing (Section 4), one QP per workgroup; workgroup b uses the
 // b-th workspace slot.  QPs that did not reach "solved" are skipped.
-constexpr int kPolishBlock = 256;
+constexpr int kPolishBlock = 512;
 template <class T>
 __global__ void __launch_bounds__(kPolishBlock) polish_wg_kernel(Batch<T> b, const int *list,
                                                                  int nlist, int slot, double *ws,

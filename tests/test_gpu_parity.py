@@ -145,6 +145,31 @@ def test_update_vectors_matches_fresh_setup(pm):
     gc.compare(qp1, x, y, info, oracle.solve(qp1))
 
 
+def test_subset_solve(pm):
+    """osqp_batch_solve_subset_async: new l, u for two QPs of a resident
+    batch (same plants, new initial states), re-solved as a subset, give the
+    oracle's solutions of the updated problems; the other QPs' results stay
+    bitwise as they were."""
+    plants = [qpgen.mpc_plant(qpgen.rng_for(3, 600 + i)) for i in range(5)]
+    qps = [qpgen.mpc(qpgen.rng_for(3, 700 + i), T=8, plant=plants[i]) for i in range(5)]
+    new = {1: qpgen.mpc(qpgen.rng_for(3, 800), T=8, plant=plants[1]),
+           3: qpgen.mpc(qpgen.rng_for(3, 801), T=8, plant=plants[3])}
+    b = pm.Batch(qps, precision="fp32")
+    b.solve()
+    before = [b.get(i) for i in range(5)]
+    for i, q in new.items():
+        b.update_vectors(i, l=q.l, u=q.u)
+    b.solve_subset(sorted(new))
+    after = [b.get(i) for i in range(5)]
+    b.close()
+    for i in range(5):
+        if i in new:
+            gc.compare(new[i], *after[i], oracle.solve(new[i]))
+        else:
+            assert np.array_equal(before[i][0], after[i][0])
+            assert np.array_equal(before[i][1], after[i][1])
+
+
 def test_deterministic_and_alone_equals_mix(pm):
     """The same QP gives bitwise-identical results when solved twice, and
     alone or inside a batch of other QPs (one QP per workgroup, fixed
