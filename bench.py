@@ -106,9 +106,10 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(workload: str):
+def stored_traffic(workload: str, shape):
     """HBM bytes per solve launch from the committed counter summary of this
-    workload, if it was taken on the current kernel sources; else None."""
+    workload, if it was taken on the current kernel sources and at the launch
+    shape (block size, lane divisor) the timed steps ran with; else None."""
     path = os.path.join(ROOT, "profiles", f"solve_wg_kernel_{workload}1024_traffic.md")
     if not os.path.exists(path):
         return None
@@ -116,10 +117,13 @@ def stored_traffic(workload: str):
     with open(path) as fh:
         for line in fh:
             if "=" in line and line.split("=")[0].strip() in ("traffic_bytes_per_launch",
-                                                              "kernel_source_sha256"):
+                                                              "kernel_source_sha256",
+                                                              "launch_shape"):
                 k, v = line.split("=", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    if shape is None or vals.get("launch_shape") != f"{shape[0]}:{shape[1]}":
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -225,6 +229,12 @@ def main():
     ap.add_argument("--serving-nmax", type=int, default=1000,
                     help="largest random-QP n in the serving mix")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the setup's launch shape (no tuning before the timed steps)")
+    ap.add_argument("--shape", default=None,
+                    help="BLOCK:LANE_DIV launch shape to apply instead of tuning")
+    ap.add_argument("--graph", action="store_true",
+                    help="solve through the replayable graph of the solve launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -242,10 +252,23 @@ def main():
     batch = pm.Batch(qps, precision="fp32", **extra)
     setup_s = time.perf_counter() - t0
     print(f"# setup {setup_s:.2f} s", file=sys.stderr, flush=True)
+    tuning = None
+    if args.shape:
+        blk, div = (int(v) for v in args.shape.split(":"))
+        batch.set_shape(blk, div)
+        tuning = {"block_size": blk, "lane_div": div, "applied": True}
+    elif not args.no_autotune:
+        t0 = time.perf_counter()
+        tuning = batch.autotune(reps=1)
+        tuning["tune_s"] = round(time.perf_counter() - t0, 3)
+        print(f"# autotune {tuning}", file=sys.stderr, flush=True)
 
     def step():
         batch.reset()
-        batch.solve()
+        if args.graph:
+            batch.solve_graph()
+        else:
+            batch.solve()
 
     for w in range(args.warmup):
         step()
@@ -269,7 +292,8 @@ def main():
     algo = algorithmic_bytes(qps, infos)
     kms = float(np.mean(kernel_ms))
     achieved = algo / (kms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload) if args.count is None else None
+    shape = (tuning["block_size"], tuning["lane_div"]) if tuning else None
+    traffic = stored_traffic(args.workload, shape) if args.count is None else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "solve_wg_kernel<float>", "kernel_ms": round(kms, 3),
@@ -287,6 +311,7 @@ def main():
         "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
         "batch_latency_ms": round(ms_per_step, 3),
         "statuses": statuses, "setup_s": round(setup_s, 3),
+        "launch": {"tuning": tuning, "graph": bool(args.graph)},
         "roofline": roofline,
     }
     if not args.no_baselines:

@@ -40,6 +40,7 @@ typedef double osqp_float;
 #define OSQP_ERR_NOT_SETUP 10     /* NULL handle or missing data            */
 #define OSQP_ERR_INDEX 11         /* problem index / ticket out of range    */
 #define OSQP_ERR_NO_DEVICE 12     /* no HIP device visible                   */
+#define OSQP_ERR_UNSUPPORTED 13   /* operation not available for this batch  */
 
 /* ---- solve status (info.status), Sections 3.3-3.4 --------------------- */
 #define OSQP_SOLVED 1
@@ -102,7 +103,9 @@ typedef struct {
   osqp_int precision;      /* OSQP_PRECISION_*, default FP32_MIXED          */
   osqp_int linsys;         /* OSQP_LINSYS_*, default AUTO                    */
   osqp_int pcg_max_iter;   /* PCG iterations per ADMM step, default 50       */
-  osqp_int block_size;     /* threads per workgroup, 0 = autotuned           */
+  osqp_int block_size;     /* threads per workgroup, 0 = chosen by size     */
+                           /* (512 for long passes, else 256; the autotuner */
+                           /* may change it); else fixed, a multiple of 64  */
   void *stream;            /* hipStream_t to run on, NULL = own stream       */
 } osqp_settings;
 
@@ -122,6 +125,15 @@ typedef struct {
    * PCG (start pass and iterations), ADMM update pass, FP64 checks */
   osqp_float factor_time, pcg_time, update_time, check_time;
 } osqp_info;
+
+/* Outcome of osqp_batch_autotune. */
+typedef struct {
+  osqp_int block_size;     /* threads per workgroup chosen                   */
+  osqp_int lane_div;       /* lanes per row ~ mean row length / lane_div      */
+  osqp_int trials;         /* launch shapes timed                            */
+  osqp_float default_ms;   /* device time of a cold solve, setup shape       */
+  osqp_float best_ms;      /* device time of a cold solve, chosen shape      */
+} osqp_tuning;
 
 typedef struct osqp_batch osqp_batch;
 typedef struct osqp_batch osqp_solver;   /* a single QP is a batch of one */
@@ -196,6 +208,35 @@ osqp_int osqp_batch_solve_async(osqp_batch *b);
  * results after osqp_batch_sync. */
 osqp_int osqp_batch_solve_subset_async(osqp_batch *b, const osqp_int *idx, osqp_int count);
 osqp_int osqp_batch_sync(osqp_batch *b);
+/* Enqueue the whole-batch solve as one replay of a HIP graph (counter reset,
+ * the persistent workgroup solve, polishing), built on the first call for the
+ * batch's current launch shape and rebuilt after osqp_batch_autotune.  Same
+ * results as osqp_batch_solve_async; results after osqp_batch_sync.  For
+ * callers that replay the solve of resident QPs many times (Section 6:
+ * parametric re-solves after update_vectors / warm_start).  Returns
+ * OSQP_ERR_UNSUPPORTED when the batch holds QPs solved by the whole grid (their
+ * launch is cooperative); osqp_batch_last_kernel_ms then spans the graph. */
+osqp_int osqp_batch_solve_graph_async(osqp_batch *b);
+/* Tune the launch shape of the batch solve on the batch itself: workgroup
+ * sizes 256 and 512 threads (only settings.block_size if that is nonzero)
+ * times lane divisors 8, 16, 32 and 64 (lanes per CSR row ~ the QP's mean row
+ * length / divisor, a power of two up to 64).  Each distinct shape is timed
+ * by `reps` (1..16) cold solves of the whole batch, device time from HIP
+ * events, minimum taken; the fastest shape stays for every later solve, and
+ * the batch is reset (iterates zero, scaling redone).  A larger grid gets
+ * its own per-workgroup workspace; shapes whose workspace cannot be
+ * allocated are skipped.  Results of later solves stay within the solver's
+ * tolerances but are not bit-identical across shapes (reduction order).
+ * `out` may be NULL. */
+osqp_int osqp_batch_autotune(osqp_batch *b, osqp_int reps, osqp_tuning *out);
+/* Apply a launch shape directly (for instance one osqp_batch_autotune chose
+ * for batches of the same kind earlier): block_size a multiple of 64 in
+ * [64, 512] (equal to settings.block_size if that is nonzero), lane_div in
+ * [1, 1024].  Waits for the batch's stream; iterates, results and the
+ * scaling are kept (osqp_batch_reset redoes the scaling, whose sums then
+ * run in the new shape's order);  OSQP_ERR_SETTINGS for a shape out of range, OSQP_ERR_ALLOC when the
+ * larger grid's workspace cannot be allocated (the old shape then stays). */
+osqp_int osqp_batch_set_shape(osqp_batch *b, osqp_int block_size, osqp_int lane_div);
 /* Re-run the device-side Ruiz scaling from the resident unscaled data and
  * reset every iterate to zero (a fresh solve of the same problems). */
 osqp_int osqp_batch_reset(osqp_batch *b);

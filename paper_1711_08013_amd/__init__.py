@@ -20,7 +20,7 @@ STATUS = {1: "solved", 2: "primal_infeasible", 3: "dual_infeasible",
           4: "max_iter_reached", 5: "time_limit_reached", 6: "unsolved"}
 ERRORS = {0: "ok", 1: "dim", 2: "csr", 3: "p_not_upper", 4: "data_nonfinite", 5: "l_gt_u",
           6: "settings", 7: "alloc", 8: "budget", 9: "device", 10: "not_setup",
-          11: "index", 12: "no_device"}
+          11: "index", 12: "no_device", 13: "unsupported"}
 PRECISION = {"fp64": 0, "fp32": 1}
 LINSYS = {"auto": 0, "pcg": 1, "dense": 2, "lowrank": 3}
 
@@ -31,6 +31,7 @@ EXPORTS = [
     "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_get_solution",
     "osqp_get_info", "osqp_cleanup", "osqp_batch_setup", "osqp_batch_solve",
     "osqp_batch_solve_async", "osqp_batch_solve_subset_async", "osqp_batch_sync",
+    "osqp_batch_solve_graph_async", "osqp_batch_autotune", "osqp_batch_set_shape",
     "osqp_batch_reset",
     "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_get",
     "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_get_factor",
@@ -75,6 +76,11 @@ class _Info(ctypes.Structure):
                 ("obj_val", "prim_res", "dual_res", "eps_prim", "eps_dual", "rho_bar",
                  "setup_time", "solve_time", "polish_time", "factor_time", "pcg_time",
                  "update_time", "check_time")]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("block_size", "lane_div", "trials")] + \
+               [(k, ctypes.c_double) for k in ("default_ms", "best_ms")]
 
 
 _lib = None
@@ -214,6 +220,23 @@ class Batch:
 
     def sync(self):
         _check(lib().osqp_batch_sync(self._h), "osqp_batch_sync")
+
+    def solve_graph(self):
+        """Solve through the replayable graph of the solve launches."""
+        _check(lib().osqp_batch_solve_graph_async(self._h), "osqp_batch_solve_graph_async")
+        self.sync()
+
+    def autotune(self, reps: int = 1) -> dict:
+        """Time the launch shapes on this batch and keep the fastest (resets it)."""
+        t = _Tuning()
+        _check(lib().osqp_batch_autotune(self._h, int(reps), ctypes.byref(t)),
+               "osqp_batch_autotune")
+        return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+    def set_shape(self, block_size: int, lane_div: int):
+        """Apply a launch shape (workgroup size, lane divisor) directly."""
+        _check(lib().osqp_batch_set_shape(self._h, int(block_size), int(lane_div)),
+               "osqp_batch_set_shape")
 
     def reset(self):
         _check(lib().osqp_batch_reset(self._h), "osqp_batch_reset")

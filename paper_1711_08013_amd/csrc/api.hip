@@ -93,11 +93,11 @@ int check_settings(const osqp_settings &s) {
   return OSQP_OK;
 }
 
-int pow2_lanes(double avg) {
-  // lanes per row: about a sixteenth of the average row length (one round of
-  // four 16-byte chunks per lane), a power of two in [1, 64]
+int pow2_lanes(double avg, int div) {
+  // lanes per row: about avg/div, a power of two in [1, 64]; the default
+  // divisor 16 gives each lane one round of four 16-byte chunks
   int L = 1;
-  while (L < 64 && 16.0 * L < avg) L <<= 1;
+  while (L < 64 && double(div) * L < avg) L <<= 1;
   return L;
 }
 
@@ -153,6 +153,23 @@ struct osqp_batch {
   double *d_partials = nullptr;
   GridBarrier *d_bar = nullptr;
   int block = 256, grid_wg = 0, grid_coop = 0, coop_block = 256;
+  int cu_count = 0;
+  // lanes per row follow the mean row length / lane_div (tunable); the means
+  // of each QP are kept so the lane counts can be rederived
+  int lane_div = 16;
+  std::vector<double> avg_mrow, avg_col;
+  // workspace of a tuned grid larger than the one sized at setup
+  void *x_dws = nullptr, *x_lws = nullptr;
+  // replayable graph of the solve launches (built on first use)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  Batch<double> g_bd{};
+  Batch<float> g_bf{};
+  struct GraphArgs {
+    int *counter; int ncounters; GridBarrier *bar;
+    int *list; int nlist; int slot;
+    int *plist; int np; int pslot; double *pws; long long pstride; int rmax;
+  } g_args{};
   // polishing workspace (one slot per resident polish workgroup)
   std::vector<int> polish_list;
   int *d_polish = nullptr;
@@ -162,7 +179,7 @@ struct osqp_batch {
   // results on the host
   std::vector<QPState> st;
   std::vector<double> xo, yo;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   double setup_time = 0.0, last_solve_time = 0.0;
   double wall_tick_s = 1e-8;
   bool solved_once = false;
@@ -350,6 +367,7 @@ int launch_solve(osqp_batch *b) {
     polish_wg_kernel<T><<<b->polish_slots, kPolishBlock, 0, b->stream>>>(
         B, b->d_polish, nl, 2, b->d_pws, b->pws_stride, b->polish_rmax);
   }
+  HIPCHK(hipEventRecord(b->ev2, b->stream));
   HIPCHK(hipGetLastError());
   return OSQP_OK;
 }
@@ -388,6 +406,199 @@ int launch_subset(osqp_batch *b, const std::vector<int> &idx, const std::vector<
   return OSQP_OK;
 }
 
+// ---- launch shapes and their tuning ----------------------------------------
+void drop_graph(osqp_batch *b) {
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+}
+
+// Give the batch a workgroup size and a lane divisor: the solve grid follows
+// the occupancy of that size, the per-workgroup workspaces grow when the grid
+// does, and every QP's lanes per row are rederived and uploaded.  The stream
+// is idle on return.
+template <class T>
+int apply_shape(osqp_batch *b, int block, int div) {
+  int per_cu = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<T>, block, 0));
+  const int grid = b->cu_count * std::max(1, per_cu);
+  Batch<T> &B = batch_of<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (B.dws && grid > b->dws_slots) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (size_t)b->dws_stride * grid) != hipSuccess) return OSQP_ERR_ALLOC;
+    if (b->x_dws) HIPCHK(hipFree(b->x_dws));
+    b->x_dws = p;
+    B.dws = static_cast<T *>(p);
+    b->dws_slots = grid;
+  }
+  if (B.lws && grid > b->lws_slots) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * (size_t)b->lws_stride * grid) != hipSuccess)
+      return OSQP_ERR_ALLOC;
+    if (b->x_lws) HIPCHK(hipFree(b->x_lws));
+    b->x_lws = p;
+    B.lws = static_cast<double *>(p);
+    b->lws_slots = grid;
+  }
+  b->block = block;
+  b->grid_wg = grid;
+  b->lane_div = div;
+  for (int k = 0; k < b->nq; ++k) {
+    b->desc[k].lm = pow2_lanes(b->avg_mrow[k], div);
+    b->desc[k].ln = pow2_lanes(b->avg_col[k], div);
+  }
+  HIPCHK(hipMemcpyAsync((void *)B.desc, b->desc.data(), sizeof(QPDesc) * b->nq, hipMemcpyHostToDevice,
+                        b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  drop_graph(b);
+  return OSQP_OK;
+}
+
+// Device time (ms) of one cold solve of the whole batch, polishing included.
+template <class T>
+int time_cold_solve(osqp_batch *b, double *ms) {
+  int rc = osqp_batch_reset(b);
+  if (rc) return rc;
+  rc = launch_solve<T>(b);
+  if (rc) return rc;
+  rc = osqp_batch_sync(b);
+  if (rc) return rc;
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, b->ev0, b->ev2));
+  *ms = t;
+  return OSQP_OK;
+}
+
+// Try the workgroup sizes {256, 512} (only the one fixed in the settings,
+// if any) and lane divisors {8, 16, 32, 64}; shapes that give the same lanes at
+// the same size are timed once.  Each shape is timed on `reps` cold solves
+// (minimum taken); the fastest stays and the batch is reset.
+template <class T>
+int autotune_impl(osqp_batch *b, int reps, osqp_tuning *out) {
+  static const int kBlocks[] = {256, 512};
+  static const int kDivs[] = {8, 16, 32, 64};
+  const int b0 = b->block, d0 = b->lane_div;
+  std::vector<std::pair<int, int>> cand{{b0, d0}};
+  for (int bl : kBlocks) {
+    if (b->set.block_size && bl != b->set.block_size) continue;
+    for (int dv : kDivs)
+      if (!(bl == b0 && dv == d0)) cand.push_back({bl, dv});
+  }
+  double warm = 0.0;
+  int rc = time_cold_solve<T>(b, &warm);   // first launches load code; untimed
+  if (rc) return rc;
+  std::vector<std::pair<int, std::vector<int>>> seen;
+  double best = INFINITY, first = INFINITY;
+  int bb = b0, bd = d0, trials = 0;
+  for (const auto &c : cand) {
+    std::vector<int> lanes(2 * (size_t)b->nq);
+    for (int k = 0; k < b->nq; ++k) {
+      lanes[2 * k] = pow2_lanes(b->avg_mrow[k], c.second);
+      lanes[2 * k + 1] = pow2_lanes(b->avg_col[k], c.second);
+    }
+    bool dup = false;
+    for (const auto &sg : seen) dup |= (sg.first == c.first && sg.second == lanes);
+    if (dup) continue;
+    seen.push_back({c.first, lanes});
+    rc = apply_shape<T>(b, c.first, c.second);
+    if (rc == OSQP_ERR_ALLOC) continue;   // a grid whose workspace does not fit
+    if (rc) return rc;
+    double t = INFINITY;
+    for (int r = 0; r < reps; ++r) {
+      double ms = 0.0;
+      if ((rc = time_cold_solve<T>(b, &ms)) != OSQP_OK) return rc;
+      t = std::min(t, ms);
+    }
+    if (trials == 0) first = t;
+    ++trials;
+    if (t < best) { best = t; bb = c.first; bd = c.second; }
+  }
+  if ((rc = apply_shape<T>(b, bb, bd)) != OSQP_OK) return rc;
+  if ((rc = osqp_batch_reset(b)) != OSQP_OK) return rc;
+  if (out) {
+    out->block_size = bb;
+    out->lane_div = bd;
+    out->trials = trials;
+    out->default_ms = first;
+    out->best_ms = best;
+  }
+  return OSQP_OK;
+}
+
+// ---- graph of the solve launches ----------------------------------------------
+template <class T>
+Batch<T> &graph_batch_of(osqp_batch *b);
+template <>
+Batch<double> &graph_batch_of<double>(osqp_batch *b) { return b->g_bd; }
+template <>
+Batch<float> &graph_batch_of<float>(osqp_batch *b) { return b->g_bf; }
+
+// Build the graph: counter reset (a fill kernel, no memset node), the
+// workgroup solve, polishing.  Its kernel arguments live in the batch.  Only
+// batches without whole-grid QPs (their launch is cooperative) qualify.
+template <class T>
+int build_graph(osqp_batch *b) {
+  if (!b->big_list.empty()) return OSQP_ERR_UNSUPPORTED;
+  drop_graph(b);
+  Batch<T> &B = graph_batch_of<T>(b);
+  B = batch_of<T>(b);
+  B.set = b->dev_settings();
+  osqp_batch::GraphArgs &g = b->g_args;
+  g.counter = B.counter; g.ncounters = 64; g.bar = nullptr;
+  g.list = b->d_small; g.nlist = (int)b->small_list.size(); g.slot = 1;
+  g.plist = b->d_polish; g.np = (int)b->polish_list.size(); g.pslot = 2;
+  g.pws = b->d_pws; g.pstride = b->pws_stride; g.rmax = b->polish_rmax;
+  auto fail = [&](hipError_t e) { drop_graph(b); return e == hipSuccess ? OSQP_OK : OSQP_ERR_DEVICE; };
+  hipError_t e = hipGraphCreate(&b->graph, 0);
+  if (e != hipSuccess) return fail(e);
+  hipGraphNode_t n0 = nullptr, n1 = nullptr, n2 = nullptr;
+  {
+    void *args[] = {&g.counter, &g.ncounters, &g.bar};
+    hipKernelNodeParams kp{};
+    kp.func = (void *)reset_counters_kernel;
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.kernelParams = args;
+    if ((e = hipGraphAddKernelNode(&n0, b->graph, nullptr, 0, &kp)) != hipSuccess) return fail(e);
+  }
+  hipGraphNode_t last = n0;
+  if (g.nlist > 0) {
+    void *args[] = {&B, &g.list, &g.nlist, &g.slot};
+    hipKernelNodeParams kp{};
+    kp.func = (void *)solve_wg_kernel<T>;
+    kp.gridDim = dim3(std::max(1, std::min(g.nlist, b->grid_wg)));
+    kp.blockDim = dim3(b->block);
+    kp.kernelParams = args;
+    if ((e = hipGraphAddKernelNode(&n1, b->graph, &last, 1, &kp)) != hipSuccess) return fail(e);
+    last = n1;
+  }
+  if (b->set.polish && g.np > 0) {
+    void *args[] = {&B, &g.plist, &g.np, &g.pslot, &g.pws, &g.pstride, &g.rmax};
+    hipKernelNodeParams kp{};
+    kp.func = (void *)polish_wg_kernel<T>;
+    kp.gridDim = dim3(b->polish_slots);
+    kp.blockDim = dim3(kPolishBlock);
+    kp.kernelParams = args;
+    if ((e = hipGraphAddKernelNode(&n2, b->graph, &last, 1, &kp)) != hipSuccess) return fail(e);
+  }
+  if ((e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return fail(e);
+  return OSQP_OK;
+}
+
+template <class T>
+int launch_graph(osqp_batch *b) {
+  if (!b->gexec) {
+    const int rc = build_graph<T>(b);
+    if (rc) return rc;
+  }
+  HIPCHK(hipEventRecord(b->ev0, b->stream));
+  HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+  HIPCHK(hipEventRecord(b->ev1, b->stream));
+  HIPCHK(hipEventRecord(b->ev2, b->stream));
+  return OSQP_OK;
+}
+
 int fetch_results(osqp_batch *b) {
   const Batch<double> &B = b->bd;
   const QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
@@ -418,6 +629,11 @@ void destroy(osqp_batch *b) {
   if (b->d_bar) (void)hipFree(b->d_bar);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->ev2) (void)hipEventDestroy(b->ev2);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->x_dws) (void)hipFree(b->x_dws);
+  if (b->x_lws) (void)hipFree(b->x_lws);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
@@ -454,7 +670,8 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     }
     b->own_stream = true;
   }
-  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess ||
+      hipEventCreate(&b->ev2) != hipSuccess) {
     destroy(b);
     return OSQP_ERR_DEVICE;
   }
@@ -487,6 +704,7 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
   else
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_wg_kernel<float>, b->block, 0);
   per_cu = std::max(1, per_cu);
+  b->cu_count = prop.multiProcessorCount;
   b->grid_wg = prop.multiProcessorCount * per_cu;
   b->coop_block = 256;
   int coop_per_cu = 1;
@@ -500,6 +718,8 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
   b->grid_coop = prop.multiProcessorCount * std::min(1, std::max(1, coop_per_cu));
   // ---- sizes, offsets, patterns (host) ------------------------------------
   b->desc.resize(count);
+  b->avg_mrow.resize(count);
+  b->avg_col.resize(count);
   std::vector<int64_t> pfull_nnz(count);
   for (int k = 0; k < count; ++k) {
     const osqp_problem &p = probs[k];
@@ -520,8 +740,10 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       const int len = p.A.indptr[i + 1] - p.A.indptr[i];
       if (len >= 2) { multi_nnz += len; ++multi_cnt; }
     }
-    d.lm = pow2_lanes(multi_cnt > 0 ? double(multi_nnz) / double(multi_cnt) : 1.0);
-    d.ln = pow2_lanes(double(pfull_nnz[k] + p.A.nnz) / p.n);
+    b->avg_mrow[k] = multi_cnt > 0 ? double(multi_nnz) / double(multi_cnt) : 1.0;
+    b->avg_col[k] = double(pfull_nnz[k] + p.A.nnz) / p.n;
+    d.lm = pow2_lanes(b->avg_mrow[k], b->lane_div);
+    d.ln = pow2_lanes(b->avg_col[k], b->lane_div);
     d.dense_off = 0;
     // entry ranges start on multiples of 4, so 16-byte loads of four
     // entries stay aligned (the gap entries are zero and never counted)
@@ -891,6 +1113,7 @@ const char *osqp_error_string(osqp_int code) {
     case OSQP_ERR_NOT_SETUP: return "handle or data missing";
     case OSQP_ERR_INDEX: return "index out of range";
     case OSQP_ERR_NO_DEVICE: return "no HIP device";
+    case OSQP_ERR_UNSUPPORTED: return "operation not available for this batch";
     default: return "unknown error";
   }
 }
@@ -961,6 +1184,39 @@ osqp_int osqp_batch_solve_subset_async(osqp_batch *b, const osqp_int *idx, osqp_
     return b->fp64 ? launch_subset<double>(b, list, pol) : launch_subset<float>(b, list, pol);
   } catch (...) {
     return OSQP_ERR_DEVICE;
+  }
+}
+
+osqp_int osqp_batch_solve_graph_async(osqp_batch *b) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  try {
+    return b->fp64 ? launch_graph<double>(b) : launch_graph<float>(b);
+  } catch (...) {
+    return OSQP_ERR_DEVICE;
+  }
+}
+
+osqp_int osqp_batch_autotune(osqp_batch *b, osqp_int reps, osqp_tuning *out) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (reps < 1 || reps > 16) return OSQP_ERR_SETTINGS;
+  try {
+    return b->fp64 ? autotune_impl<double>(b, reps, out) : autotune_impl<float>(b, reps, out);
+  } catch (...) {
+    return OSQP_ERR_ALLOC;
+  }
+}
+
+osqp_int osqp_batch_set_shape(osqp_batch *b, osqp_int block_size, osqp_int lane_div) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  if (block_size < 64 || block_size > kMaxBlock || block_size % 64 || lane_div < 1 ||
+      lane_div > 1024)
+    return OSQP_ERR_SETTINGS;
+  if (b->set.block_size && block_size != b->set.block_size) return OSQP_ERR_SETTINGS;
+  try {
+    return b->fp64 ? apply_shape<double>(b, block_size, lane_div)
+                   : apply_shape<float>(b, block_size, lane_div);
+  } catch (...) {
+    return OSQP_ERR_ALLOC;
   }
 }
 
