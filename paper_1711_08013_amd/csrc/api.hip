@@ -821,7 +821,10 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
           d.dld = ldS;
           d.dense_off = b->lr_total;
           b->lr_total += lo.total;
+          // scratch of the workgroup: G (R x n8) while S is formed, then
+          // U (R x ldS) and the inversion's blocks
           gmax = std::max(gmax, (int64_t)R * ((n + 7) & ~7));
+          gmax = std::max(gmax, (int64_t)R * ldS + spd_inverse_extra(R));
           continue;
         }
       }

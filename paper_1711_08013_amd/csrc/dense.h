@@ -334,6 +334,96 @@ __device__ __forceinline__ void dense_invert_diag(const WGTeam &tm, DenseLDS<T> 
   }
 }
 
+// C (ni x nj, row-major, ldc) += scale * A B' with A (ni x K) and B (nj x K)
+// row-major (lda, ldb), ni, nj <= kTS: depth panels of kNB staged in LDS,
+// the vector-ALU tile product.
+__device__ __forceinline__ void tile_nt_acc(const WGTeam &tm, DenseLDS<double> &s, double *C,
+                                            int ldc, const double *A, int lda, const double *B,
+                                            int ldb, int ni, int nj, int K, double scale) {
+  for (int k0 = 0; k0 < K; k0 += kNB) {
+    const int kd = min(kNB, K - k0);
+    for (int e = tm.tid; e < kTS * kNB; e += tm.nt) {
+      const int r = e / kNB, t = e % kNB;
+      s.pa[r][t] = (r < ni && t < kd) ? A[(size_t)r * lda + k0 + t] : 0.0;
+      s.pb[r][t] = (r < nj && t < kd) ? B[(size_t)r * ldb + k0 + t] : 0.0;
+    }
+    tm.sync();
+    tile_gemm_nt_valu<double>(tm, s, C, ldc, 0, 0, ni, nj, kd, scale, false);
+    tm.sync();
+  }
+}
+
+// Doubles of scratch dense_spd_inverse needs besides U (R x ld).
+__host__ __device__ inline int64_t spd_inverse_extra(int R) {
+  return (int64_t)((R + 63) / 64 + 1) * 4096;
+}
+
+// Inverse of an SPD matrix from its Cholesky factor: S (R x R, row-major, ld
+// a multiple of 8, the factor L in its lower triangle) is overwritten by the
+// full symmetric S^-1 (zero in the padding columns R..ld-1).  Scratch: U
+// (R x ld) and `work` (spd_inverse_extra(R) doubles).  With 64 x 64 blocks,
+// U = (L^-1)' is built block row by block row: U_jj = (L_jj^-1)' from the
+// inverted diagonal blocks, and for i > j
+//     U_ji = -(sum_{k=j..i-1} U_jk L_ik') (L_ii^-1)'
+// (the transpose of the block forward substitution for L X = I).  Then
+// S^-1 = L^-T L^-1 = U U' (lower triangle by the Gram routine, mirrored).
+__device__ __forceinline__ void dense_spd_inverse(const WGTeam &tm, DenseLDS<double> &s, double *S,
+                                                  int ld, int R, double *U, double *work) {
+  const int nb = (R + 63) / 64;
+  double *Linv = work, *W = work + (size_t)nb * 4096;
+  dense_invert_diag<double>(tm, s, S, ld, R, Linv);
+  for (size_t e = tm.tid; e < (size_t)R * ld; e += tm.nt) U[e] = 0.0;
+  tm.sync();
+  for (int j = 0; j < nb; ++j) {
+    const int j0 = 64 * j, nj = min(64, R - j0);
+    const double *Lj = Linv + (size_t)j * 4096;
+    for (int e = tm.tid; e < nj * nj; e += tm.nt) {
+      const int a = e / nj, b = e % nj;
+      U[(size_t)(j0 + a) * ld + j0 + b] = Lj[b * 64 + a];
+    }
+    tm.sync();
+    for (int i = j + 1; i < nb; ++i) {
+      const int i0 = 64 * i, ni = min(64, R - i0);
+      for (int e = tm.tid; e < 4096; e += tm.nt) W[e] = 0.0;
+      tm.sync();
+      for (int k = j; k < i; ++k)   // blocks k < i are full (64 wide)
+        tile_nt_acc(tm, s, W, 64, U + (size_t)j0 * ld + 64 * k, ld, S + (size_t)i0 * ld + 64 * k,
+                    ld, nj, ni, 64, 1.0);
+      tile_nt_acc(tm, s, U + (size_t)j0 * ld + i0, ld, W, 64, Linv + (size_t)i * 4096, 64, nj, ni,
+                  ni, -1.0);
+    }
+  }
+  dense_gram_lower(tm, s, U, ld, R, R, S, ld);
+  // upper triangle from the lower one (only upper entries are written)
+  for (size_t e = tm.tid; e < (size_t)R * ld; e += tm.nt) {
+    const int i = (int)(e / ld), j = (int)(e % ld);
+    if (j > i) S[e] = j < R ? S[(size_t)j * ld + i] : 0.0;
+  }
+  tm.sync();
+}
+
+// f(r, sum_c M[r][c] y[c]) for the R rows of a dense matrix (row-major, ld
+// a multiple of 8, rows 16-byte aligned, readable up to column ld-1; y
+// readable up to index R rounded up to 8): 16 lanes per row, two columns per
+// 16-byte load, fixed summation order.
+template <class F>
+__device__ __forceinline__ void dense_rows_matvec(const WGTeam &tm, const double *M, int ld, int R,
+                                                  const double *y, F &&f) {
+  const int sub = tm.tid & 15, grp = tm.tid >> 4, ngrp = tm.nt >> 4;
+  for (int r = grp; r < R; r += ngrp) {
+    const double *row = M + (size_t)r * ld;
+    double a0 = 0.0, a1 = 0.0;
+    for (int c = 2 * sub; c < R; c += 32) {
+      const double2 mv = *reinterpret_cast<const double2 *>(row + c);
+      const double y0 = y[c], y1 = y[c + 1];
+      a0 += mv.x * y0;
+      a1 += c + 1 < R ? mv.y * y1 : 0.0;
+    }
+    const double t = group_sum(a0 + a1, 16);
+    if (sub == 0) f(r, t);
+  }
+}
+
 // Four consecutive T from a 16-byte-aligned address.
 template <class T>
 __device__ __forceinline__ void load4(const T *p, T &a, T &b, T &c, T &d) {

@@ -27,19 +27,18 @@ struct QPDesc {
 };
 
 // Offsets (doubles) inside one QP's low-rank block: Delta^-1 at 0, then u
-// (n), the capacitance matrix S (R x ldS, lower), the inverses of its 64 x 64
-// diagonal blocks, w compact (R) and w scattered by row of A (m).  Every
-// part starts on a multiple of 8 doubles.
+// (n), the capacitance matrix S (R x ldS; formed and factored there, then
+// replaced by the full symmetric S^-1), w compact (R) and w scattered by row
+// of A (m).  Every part starts on a multiple of 8 doubles.
 struct LRLayout {
-  int64_t u, S, Sinv, wc, wr, total;
+  int64_t u, S, wc, wr, total;
 };
 __host__ __device__ inline LRLayout lr_layout(int n, int m, int R, int ldS) {
   const int64_t n8 = (n + 7) & ~7, m8 = (m + 7) & ~7, R8 = (R + 7) & ~7;
   LRLayout L;
   L.u = n8;
   L.S = L.u + n8;
-  L.Sinv = L.S + (int64_t)R * ldS;
-  L.wc = L.Sinv + (int64_t)((R + 63) / 64) * 64 * 64;
+  L.wc = L.S + (int64_t)R * ldS;
   L.wr = L.wc + R8;
   L.total = L.wr + m8;
   return L;

@@ -468,9 +468,10 @@ __device__ __forceinline__ void precondition_dense(const WGTeam &tm, const QPVie
 // Delta = diag(P) + sigma + sum over single-entry rows of rho_i a_ij^2.
 // The Woodbury identity gives K^-1 r = u - Delta^-1 B' S^-1 B u with
 // u = Delta^-1 r and the R x R capacitance matrix S = I + B Delta^-1 B',
-// factored once per rho-bar in FP64 (S = G G' + I, G = B Delta^-1/2 formed
-// densely in the workgroup's scratch).  This is the same reduced system the
-// dense factor solves, at O(R^2 n) set-up and O(nnz(A_m)) per apply.
+// formed, factored and inverted once per rho-bar in FP64 (S = G G' + I,
+// G = B Delta^-1/2 formed densely in the workgroup's scratch).  This is the
+// same reduced system the dense factor solves, at O(R^2 n) set-up and
+// O(nnz(A_m) + R^2) per apply.
 // ------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const QPView<T> &v,
@@ -478,7 +479,7 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
                                                         double sigma, double rho_bar) {
   const int n = v.n, m = v.m, R = v.mr_cnt, ldS = v.ld, ldg = (n + 7) & ~7;
   const LRLayout lo = lr_layout(n, m, R, ldS);
-  double *dinv = v.lr, *S = v.lr + lo.S, *Sinv = v.lr + lo.Sinv, *wr = v.lr + lo.wr;
+  double *dinv = v.lr, *S = v.lr + lo.S, *wr = v.lr + lo.wr;
   auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
   for (int j = tm.tid; j < n; j += tm.nt) {
     double a = sigma;
@@ -510,7 +511,9 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
   for (int r = tm.tid; r < R; r += tm.nt) S[(size_t)r * ldS + r] += 1.0;
   tm.sync();
   const bool ok = dense_cholesky<double>(tm, s, S, ldS, R);
-  if (ok) dense_invert_diag<double>(tm, s, S, ldS, R, Sinv);
+  // S^-1 explicitly (G, no longer needed, is the scratch): each application
+  // is then one dense matrix-vector product instead of two block sweeps
+  if (ok) dense_spd_inverse(tm, s, S, ldS, R, G, G + (size_t)R * ldS);
   return ok;
 }
 
@@ -519,17 +522,16 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
 // the same K).  u = Delta^-1 r is formed here from r (T), or was left in the
 // block's u by the caller (u_ready, from the FP64 residual).  The result goes
 // to d (rounded to T) or, to_xt, is added to the FP64 iterate x~ (the direct
-// solve).  With an LDS stage (u and the scattered w in LDS, outside the part
-// of s that the triangular solve uses) the gathers of both passes hit LDS.
+// solve).  With an LDS stage (u and the scattered w in LDS) the gathers of
+// both sparse passes hit LDS.
 template <class T>
 __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPView<T> &v,
-                                                     DenseLDS<double> &s, double rho_bar,
-                                                     double *stage = nullptr, bool u_ready = false,
-                                                     bool to_xt = false) {
+                                                     double rho_bar, double *stage = nullptr,
+                                                     bool u_ready = false, bool to_xt = false) {
   const int n = v.n, m = v.m, R = v.mr_cnt, ldS = v.ld;
   const int n8 = (n + 7) & ~7;
   const LRLayout lo = lr_layout(n, m, R, ldS);
-  const double *dinv = v.lr, *S = v.lr + lo.S, *Sinv = v.lr + lo.Sinv;
+  const double *dinv = v.lr, *Sinv = v.lr + lo.S;
   double *wc = v.lr + lo.wc, *ug = v.lr + lo.u;
   auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
   auto body = [&](double *u, double *wr, bool zero_wr) __attribute__((always_inline)) {
@@ -559,11 +561,11 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
       }
     }
     tm.sync();
-    dense_solve_llt<double>(tm, s, S, ldS, R, Sinv, wc);
-    for (int r = tm.tid; r < R; r += tm.nt) {
+    // w = S^-1 (B u), scattered to the rows of A with the factor R_m^1/2
+    dense_rows_matvec(tm, Sinv, ldS, R, wc, [&](int r, double w) __attribute__((always_inline)) {
       const int i = v.mrows[r];
-      wr[i] = sqrt(rho_i(i)) * wc[r];
-    }
+      wr[i] = sqrt(rho_i(i)) * w;
+    });
     tm.sync();
     // K^-1 r = u - Delta^-1 B' w  (B' w through the rows of A'; zero on
     // single-entry rows)
@@ -624,7 +626,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   auto apply_pre = [&]() __attribute__((always_inline)) {
     if constexpr (std::is_same<Team, WGTeam>::value) {
       if (pre_kind == 1) precondition_dense(tm, v, *dl);
-      else precondition_lowrank(tm, v, *dl64, rho_bar, stage);
+      else precondition_lowrank(tm, v, rho_bar, stage);
     }
   };
   bool use_dense = false;
@@ -743,7 +745,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         tm.template reduce<0, 1>(red + 1);
         dense_skip = bnorm >= 0.0 && red[1] <= pcg_tol(bnorm);
         if (direct) {
-          if (!dense_skip) precondition_lowrank(tm, v, *dl64, rho_bar, stage, true, true);
+          if (!dense_skip) precondition_lowrank(tm, v, rho_bar, stage, true, true);
         } else if (!dense_skip) {
           apply_pre();
           for (int j = tm.tid; j < n; j += tm.nt) {
