@@ -52,12 +52,19 @@ __device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Output row of register v of lane group lk (= lane / 16) of a 16x16x4
+// MFMA: the FP32 instruction returns D[4 lk + v][lane % 16], the FP64 one
+// D[lk + 4 v][lane % 16] (both take A[lane % 16][lane / 16] and
+// B[lane / 16][lane % 16]).
+template <class T>
+__device__ __forceinline__ int mfma_row(int lk, int v) {
+  return sizeof(T) == 4 ? 4 * lk + v : lk + 4 * v;
+}
+
 // C[i0.., j0..] += scale * Pa Pb' for one kTS x kTS tile, depth kd <= kNB
 // (Pa holds the i rows, Pb the j rows, both in LDS, zero-padded to kNB).
 // Matrix cores: each of the first four waves owns four 16 x 16 output
-// sub-tiles and runs 16x16x4 MFMAs over the depth.  Operand layout of the
-// 16x16x4 instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// and receives D[4 (l / 16) + v][l % 16], v = 0..3.
+// sub-tiles and runs 16x16x4 MFMAs over the depth (layout as mfma_row).
 template <class T>
 __device__ __forceinline__ void tile_gemm_nt_mfma(const WGTeam &tm, DenseLDS<T> &s, T *C, int ld,
                                                   int i0, int j0, int ni, int nj, int kd,
@@ -76,7 +83,7 @@ __device__ __forceinline__ void tile_gemm_nt_mfma(const WGTeam &tm, DenseLDS<T> 
       acc = mfma16x16x4(s.pa[si + li][k0 + lk], s.pb[sj + li][k0 + lk], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = si + 4 * lk + v, j = sj + li;
+      const int i = si + mfma_row<T>(lk, v), j = sj + li;
       if (i >= ni || j >= nj) continue;
       if (lower_only && i0 + i < j0 + j) continue;
       C[(size_t)(i0 + i) * ld + (j0 + j)] += scale * acc[v];
@@ -84,8 +91,7 @@ __device__ __forceinline__ void tile_gemm_nt_mfma(const WGTeam &tm, DenseLDS<T> 
   }
 }
 
-// Same tile update on the vector ALUs (used for double: the FP64 16x16x4
-// instruction's result layout differs from the FP32 one assumed above).
+// Same tile update on the vector ALUs.
 template <class T>
 __device__ __forceinline__ void tile_gemm_nt_valu(const WGTeam &tm, DenseLDS<T> &s, T *C,
                                                   int ld, int i0, int j0, int ni, int nj, int kd,
@@ -125,7 +131,7 @@ template <class T>
 __device__ __forceinline__ void tile_gemm_nt(const WGTeam &tm, DenseLDS<T> &s, T *C, int ld,
                                              int i0, int j0, int ni, int nj, int kd, T scale,
                                              bool lower_only) {
-  if constexpr (sizeof(T) == 4)
+  if (tm.nt >= 4 * kWave)
     tile_gemm_nt_mfma<T>(tm, s, C, ld, i0, j0, ni, nj, kd, scale, lower_only);
   else
     tile_gemm_nt_valu<T>(tm, s, C, ld, i0, j0, ni, nj, kd, scale, lower_only);
@@ -160,9 +166,9 @@ __device__ __forceinline__ void dense_syrk_tn(const WGTeam &tm, DenseLDS<T> &s, 
 // threads own a 4 x 4 block of a tile each (rows ti + 16a, columns
 // tj + 16c), so per k step a thread reads eight LDS values for sixteen FMAs.
 // Workgroups of fewer than 256 threads take several passes over a tile.
-__device__ __forceinline__ void dense_gram_lower(const WGTeam &tm, DenseLDS<double> &s,
-                                                 const double *G, int ldg, int R, int K,
-                                                 double *S, int ldS) {
+__device__ __forceinline__ void dense_gram_lower_64(const WGTeam &tm, DenseLDS<double> &s,
+                                                    const double *G, int ldg, int R, int K,
+                                                    double *S, int ldS) {
   constexpr int KC = 64;
   const int passes = tm.nt >= 256 ? 1 : (256 + tm.nt - 1) / tm.nt;
   for (int i0 = 0; i0 < R; i0 += kTS) {
@@ -215,6 +221,95 @@ __device__ __forceinline__ void dense_gram_lower(const WGTeam &tm, DenseLDS<doub
     }
   }
   tm.sync();
+}
+
+// The same product for R <= min(240, nt / 2) (nt >= 256 threads): each
+// 16-deep k panel holds all R rows in LDS, so G is read once per pass
+// instead of once per output tile; the lower 16 x 16 sub-tiles are dealt to
+// the waves, at most four per wave and pass (their accumulators stay in
+// registers), FP64 16x16x4 MFMAs.  The next panel is loaded into registers
+// (16-byte loads: ldg a multiple of 2, rows 16-byte aligned, readable up to
+// column K rounded up to 2) while the current one is used.
+constexpr int kGramPanelMaxR = 240;
+__device__ __forceinline__ void dense_gram_lower_panel(const WGTeam &tm, DenseLDS<double> &s,
+                                                       const double *G, int ldg, int R, int K,
+                                                       double *S, int ldS) {
+  constexpr int KC = 16, LDP = KC + 1, QW = 4, NP = 4;   // 8 R <= NP nt (see the dispatch)
+  static_assert(kGramPanelMaxR * LDP <= 2 * 64 * 65, "gram panel exceeds the block area");
+  double *P = &s.blk[0][0];
+  const int wv = tm.tid >> 6, nw = tm.nt >> 6, lane = tm.tid & (kWave - 1);
+  const int li = lane & 15, lk = lane >> 4;
+  const int nbk = (R + 15) / 16, T = nbk * (nbk + 1) / 2, npair = R * (KC / 2);
+  constexpr int PS = KC / 2;   // 16-byte pairs per panel row
+  for (int p0 = 0; p0 < T; p0 += nw * QW) {
+    int bi[QW], bj[QW];
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      const int idx = p0 + wv + nw * q;   // uniform in the wave
+      int r = 0;
+      while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+      bi[q] = idx < T ? r : -1;
+      bj[q] = idx - r * (r + 1) / 2;
+    }
+    f64x4 acc[QW];
+#pragma unroll
+    for (int q = 0; q < QW; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double2 nxt[NP];
+    auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int e = tm.tid + tm.nt * u, r = e / PS, t = 2 * (e % PS);
+        double2 x = {0.0, 0.0};
+        if (e < npair && k0 + t < K) {
+          x = *reinterpret_cast<const double2 *>(G + (size_t)r * ldg + k0 + t);
+          if (k0 + t + 1 >= K) x.y = 0.0;
+        }
+        nxt[u] = x;
+      }
+    };
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      tm.sync();
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int e = tm.tid + tm.nt * u, r = e / PS, t = 2 * (e % PS);
+        if (e < npair) {
+          P[r * LDP + t] = nxt[u].x;
+          P[r * LDP + t + 1] = nxt[u].y;
+        }
+      }
+      tm.sync();
+      if (k0 + KC < K) load(k0 + KC);
+#pragma unroll
+      for (int q = 0; q < QW; ++q) {
+        if (bi[q] < 0) continue;
+        // rows past R read stale LDS: they only reach output rows and
+        // columns past R, which are not written
+        const double *pa = P + min(16 * bi[q] + li, R - 1) * LDP + lk;
+        const double *pb = P + min(16 * bj[q] + li, R - 1) * LDP + lk;
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) acc[q] = mfma16x16x4(pa[kk], pb[kk], acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      if (bi[q] < 0) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * bi[q] + mfma_row<double>(lk, v), j = 16 * bj[q] + li;
+        if (i < R && j < R && i >= j) S[(size_t)i * ldS + j] = acc[q][v];
+      }
+    }
+  }
+  tm.sync();
+}
+
+__device__ __forceinline__ void dense_gram_lower(const WGTeam &tm, DenseLDS<double> &s,
+                                                 const double *G, int ldg, int R, int K,
+                                                 double *S, int ldS) {
+  if (tm.nt >= 4 * kWave && R <= kGramPanelMaxR && 2 * R <= tm.nt)
+    dense_gram_lower_panel(tm, s, G, ldg, R, K, S, ldS);
+  else dense_gram_lower_64(tm, s, G, ldg, R, K, S, ldS);
 }
 
 // In-place Cholesky M = L L' of the lower triangle.  Returns false (to every
@@ -336,7 +431,7 @@ __device__ __forceinline__ void dense_invert_diag(const WGTeam &tm, DenseLDS<T> 
 
 // C (ni x nj, row-major, ldc) += scale * A B' with A (ni x K) and B (nj x K)
 // row-major (lda, ldb), ni, nj <= kTS: depth panels of kNB staged in LDS,
-// the vector-ALU tile product.
+// the matrix-core tile product.
 __device__ __forceinline__ void tile_nt_acc(const WGTeam &tm, DenseLDS<double> &s, double *C,
                                             int ldc, const double *A, int lda, const double *B,
                                             int ldb, int ni, int nj, int K, double scale) {
@@ -348,7 +443,7 @@ __device__ __forceinline__ void tile_nt_acc(const WGTeam &tm, DenseLDS<double> &
       s.pb[r][t] = (r < nj && t < kd) ? B[(size_t)r * ldb + k0 + t] : 0.0;
     }
     tm.sync();
-    tile_gemm_nt_valu<double>(tm, s, C, ldc, 0, 0, ni, nj, kd, scale, false);
+    tile_gemm_nt<double>(tm, s, C, ldc, 0, 0, ni, nj, kd, scale, false);
     tm.sync();
   }
 }
@@ -404,23 +499,46 @@ __device__ __forceinline__ void dense_spd_inverse(const WGTeam &tm, DenseLDS<dou
 
 // f(r, sum_c M[r][c] y[c]) for the R rows of a dense matrix (row-major, ld
 // a multiple of 8, rows 16-byte aligned, readable up to column ld-1; y
-// readable up to index R rounded up to 8): 16 lanes per row, two columns per
-// 16-byte load, fixed summation order.
+// readable up to index R rounded up to 8).  A wave takes four rows at a
+// time, each lane two columns per 16-byte load and row, so all of a lane's
+// loads for the four rows are in flight together; fixed summation order.
 template <class F>
 __device__ __forceinline__ void dense_rows_matvec(const WGTeam &tm, const double *M, int ld, int R,
                                                   const double *y, F &&f) {
-  const int sub = tm.tid & 15, grp = tm.tid >> 4, ngrp = tm.nt >> 4;
-  for (int r = grp; r < R; r += ngrp) {
-    const double *row = M + (size_t)r * ld;
-    double a0 = 0.0, a1 = 0.0;
-    for (int c = 2 * sub; c < R; c += 32) {
-      const double2 mv = *reinterpret_cast<const double2 *>(row + c);
-      const double y0 = y[c], y1 = y[c + 1];
-      a0 += mv.x * y0;
-      a1 += c + 1 < R ? mv.y * y1 : 0.0;
+  constexpr int RU = 4;
+  const int lane = tm.tid & (kWave - 1), wv = tm.tid >> 6, nw = tm.nt >> 6;
+  for (int r0 = RU * wv; r0 < R; r0 += RU * nw) {
+    double acc[RU];
+#pragma unroll
+    for (int q = 0; q < RU; ++q) acc[q] = 0.0;
+    // 256 columns per step: two 16-byte loads per lane and row, all issued
+    // before any is used
+    for (int c0 = 0; c0 < R; c0 += 4 * kWave) {
+      double2 mv[RU][2];
+      double yv[4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = min(c0 + 2 * lane + 2 * kWave * h, (R - 1) & ~1);
+#pragma unroll
+        for (int q = 0; q < RU; ++q)
+          mv[q][h] = *reinterpret_cast<const double2 *>(M + (size_t)min(r0 + q, R - 1) * ld + c);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = c0 + 2 * lane + 2 * kWave * h;
+        yv[2 * h] = c < R ? y[c] : 0.0;
+        yv[2 * h + 1] = c + 1 < R ? y[c + 1] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < RU; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[q] += mv[q][h].x * yv[2 * h] + mv[q][h].y * yv[2 * h + 1];
     }
-    const double t = group_sum(a0 + a1, 16);
-    if (sub == 0) f(r, t);
+#pragma unroll
+    for (int q = 0; q < RU; ++q) {
+      const double t = group_sum(acc[q], kWave);
+      if (lane == 0 && r0 + q < R) f(r0 + q, t);
+    }
   }
 }
 

@@ -124,20 +124,20 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       double a = 0.0;
       for (int k = pb + rn.lane; k < pe; k += rn.L)
         if (v.pci[k] == j) a += v.p64[k];
-      for (int k = ab + rn.lane; k < ae; k += rn.L) {
-        const double e = v.at64[k];
-        a += ry[v.atci[k]] * e * e * dinv_d;
-      }
+      a += seg_sum4<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L,
+                            [&](double e, int i) __attribute__((always_inline)) {
+                              return ry[i] * e * e * dinv_d;
+                            });
       a = group_sum(a, rn.L);
       if (rn.lane == 0) Dl[j] = 1.0 / (delta + a);
     });
     tm.sync();
     for (int r = rm.g; r < R; r += rm.ng) {
       const int i = multi[r];
-      for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L) {
-        const int j = v.aci[k];
-        G[(size_t)r * n8 + j] = v.a64[k] * rs * sqrt(Dl[j]);
-      }
+      seg_each4(v.aci, v.a64, v.arp[i], v.arp[i + 1], rm.lane, rm.L,
+                [&](int j, double a) __attribute__((always_inline)) {
+                  G[(size_t)r * n8 + j] = a * rs * sqrt(Dl[j]);
+                });
     }
     tm.sync();
     dense_gram_lower(tm, s, G, n8, R, n, S, r8);

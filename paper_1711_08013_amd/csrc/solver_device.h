@@ -162,6 +162,63 @@ __device__ __forceinline__ A seg_partial4(const int *ci, const V *v, int b, int 
   return (s0 + s1) + (s2 + s3);
 }
 
+// sum over [b, e) of f(v[k], ci[k]) for the lanes of a group (not reduced),
+// with seg_partial4's chunked unconditional loads and summation order.
+template <class A, class V, class F>
+__device__ __forceinline__ A seg_sum4(const int *ci, const V *v, int b, int e, int lane, int L,
+                                      F &&f) {
+  A s0 = A(0), s1 = A(0), s2 = A(0), s3 = A(0);
+  if (e <= b) return A(0);
+  const int last = (e - 1) & ~3;
+  for (int k = (b & ~3) + 4 * lane; k < e; k += 16 * L) {
+    int c[4][4];
+    V a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = min(k + 4 * L * u, last);
+      ld4(ci + kk, c[u]);
+      ld4(v + kk, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * L * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = kk + q >= b && kk + q < e;
+        const A t = ok ? f(A(a[u][q]), c[u][q]) : A(0);
+        if (q == 0) s0 += t; else if (q == 1) s1 += t; else if (q == 2) s2 += t; else s3 += t;
+      }
+    }
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+// f(ci[k], v[k]) for every k in [b, e) on the lanes of a group, with the
+// chunked unconditional loads of seg_partial4.
+template <class V, class F>
+__device__ __forceinline__ void seg_each4(const int *ci, const V *v, int b, int e, int lane, int L,
+                                          F &&f) {
+  if (e <= b) return;
+  const int last = (e - 1) & ~3;
+  for (int k = (b & ~3) + 4 * lane; k < e; k += 16 * L) {
+    int c[4][4];
+    V a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = min(k + 4 * L * u, last);
+      ld4(ci + kk, c[u]);
+      ld4(v + kk, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * L * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (kk + q >= b && kk + q < e) f(c[u][q], a[u][q]);
+    }
+  }
+}
+
 // max_k |v[k]| s[ci[k]] over [b, e) for the lanes of a group (not reduced),
 // with the chunked unconditional loads of seg_chunks.
 template <class S>
@@ -481,30 +538,31 @@ __device__ __forceinline__ bool lowrank_form_and_factor(const WGTeam &tm, const 
   const LRLayout lo = lr_layout(n, m, R, ldS);
   double *dinv = v.lr, *S = v.lr + lo.S, *wr = v.lr + lo.wr;
   auto rho_i = [&](int i) -> double { return v.iseq[i] ? 1e3 * rho_bar : rho_bar; };
-  for (int j = tm.tid; j < n; j += tm.nt) {
-    double a = sigma;
-    for (int k = v.prp[j]; k < v.prp[j + 1]; ++k)
-      if (v.pci[k] == j) a += double(v.pv[k]);
-    for (int k = v.atrp[j]; k < v.atrp[j + 1]; ++k) {
-      const int i = v.atci[k];
-      if (v.arp[i + 1] - v.arp[i] == 1) {
-        const double e = double(v.atv[k]);
-        a += rho_i(i) * e * e;
-      }
-    }
-    dinv[j] = 1.0 / a;
-  }
+  // rho_i of the single-entry rows (0 for the others) in w's by-row slots,
+  // so that Delta is a gathered sum over the rows of A'
+  for (int i = tm.tid; i < m; i += tm.nt) wr[i] = v.arp[i + 1] - v.arp[i] == 1 ? rho_i(i) : 0.0;
   for (size_t e = tm.tid; e < (size_t)R * ldg; e += tm.nt) G[e] = 0.0;
-  for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;   // single-entry rows stay 0
   tm.sync();
+  const Rows rn(tm, v.ln);
+  rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n, [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
+    double a = 0.0;
+    for (int k = pb + rn.lane; k < pe; k += rn.L)   // P is diagonal here
+      if (v.pci[k] == j) a += double(v.pv[k]);
+    a += seg_sum4<double>(v.atci, v.atv, ab, ae, rn.lane, rn.L,
+                          [&](double e, int i) __attribute__((always_inline)) { return wr[i] * e * e; });
+    a = group_sum(a, rn.L);
+    if (rn.lane == 0) dinv[j] = 1.0 / (sigma + a);
+  });
+  tm.sync();
+  for (int i = tm.tid; i < m; i += tm.nt) wr[i] = 0.0;   // single-entry rows stay 0
   const Rows rm(tm, v.lm);
   for (int r = rm.g; r < R; r += rm.ng) {
     const int i = v.mrows[r];
     const double sr = sqrt(rho_i(i));
-    for (int k = v.arp[i] + rm.lane; k < v.arp[i + 1]; k += rm.L) {
-      const int j = v.aci[k];
-      G[(size_t)r * ldg + j] = sr * double(v.av[k]) * sqrt(dinv[j]);
-    }
+    seg_each4(v.aci, v.av, v.arp[i], v.arp[i + 1], rm.lane, rm.L,
+              [&](int j, T a) __attribute__((always_inline)) {
+                G[(size_t)r * ldg + j] = sr * double(a) * sqrt(dinv[j]);
+              });
   }
   tm.sync();
   dense_gram_lower(tm, s, G, ldg, R, n, S, ldS);
