@@ -219,6 +219,84 @@ __device__ __forceinline__ void seg_each4(const int *ci, const V *v, int b, int 
   }
 }
 
+
+// Rows t = g, g + ng, ... < cnt (CSR row rowof(t)); per lane group of L
+// lanes, sum over the row of v[k] x[ci[k]], then epi(t, i, sum, pre) with
+// pre = pro(i) loaded when the row became current.  The chunk loads of the
+// next round (of this row or of the next) are issued before the current
+// round's gathers; the summation order is seg_partial4's.
+template <class A, class V, class X, class RowOf, class Pro, class Epi>
+__device__ __forceinline__ void stream_rows(const int *rp, const int *ci, const V *v, const X *x,
+                                            int g, int ng, int cnt, int lane, int L, RowOf &&rowof,
+                                            Pro &&pro, Epi &&epi) {
+  int t = g;
+  int i = t < cnt ? rowof(t) : 0;
+  int b = t < cnt ? rp[i] : 0, e = t < cnt ? rp[i + 1] : 0;
+  int t2 = t + ng;
+  int i2 = t2 < cnt ? rowof(t2) : 0;
+  int b2 = t2 < cnt ? rp[i2] : 0, e2 = t2 < cnt ? rp[i2 + 1] : 0;
+  decltype(pro(0)) pre{};
+  if (t < cnt) pre = pro(i);
+  int kb = b & ~3;   // round base, the same for every lane of the group
+  int c[4][4];
+  V a[4][4];
+  auto load = [&](int kp, int bb, int eb, int (&cc)[4][4], V (&aa)[4][4]) __attribute__((always_inline)) {
+    if (eb <= bb) {   // empty row: nothing to read (its start may be the array's end)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { cc[u][q] = 0; aa[u][q] = V(0); }
+      return;
+    }
+    const int last = (eb - 1) & ~3;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = min(kp + 4 * L * u, last);
+      ld4(ci + kk, cc[u]);
+      ld4(v + kk, aa[u]);
+    }
+  };
+  if (t < cnt) load(kb + 4 * lane, b, e, c, a);
+  A s0 = A(0), s1 = A(0), s2 = A(0), s3 = A(0);
+  while (t < cnt) {
+    const bool same = kb + 16 * L < e;   // uniform in the group
+    const int kbn = same ? kb + 16 * L : (b2 & ~3);
+    const int bn = same ? b : b2, en = same ? e : e2;
+    const bool more = same || t2 < cnt;
+    int cn[4][4];
+    V an[4][4];
+    if (more) load(kbn + 4 * lane, bn, en, cn, an);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = kb + 4 * lane + 4 * L * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = kk + q >= b && kk + q < e;
+        const int cq = ok ? c[u][q] : 0;
+        const A aq = ok ? A(a[u][q]) : A(0);
+        const A tq = aq * A(x[cq]);
+        if (q == 0) s0 += tq; else if (q == 1) s1 += tq; else if (q == 2) s2 += tq; else s3 += tq;
+      }
+    }
+    if (!same) {
+      const A sum = group_sum((s0 + s1) + (s2 + s3), L);
+      epi(t, i, sum, pre);
+      s0 = s1 = s2 = s3 = A(0);
+      const int t3 = t2 + ng;
+      const int i3 = t3 < cnt ? rowof(t3) : 0;
+      const int b3 = t3 < cnt ? rp[i3] : 0, e3 = t3 < cnt ? rp[i3 + 1] : 0;
+      t = t2; i = i2; b = b2; e = e2;
+      t2 = t3; i2 = i3; b2 = b3; e2 = e3;
+      if (t < cnt) pre = pro(i);
+    }
+    kb = kbn;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { c[u][q] = cn[u][q]; a[u][q] = an[u][q]; }
+  }
+}
+
 // max_k |v[k]| s[ci[k]] over [b, e) for the lanes of a group (not reduced),
 // with the chunked unconditional loads of seg_chunks.
 template <class S>
@@ -604,20 +682,12 @@ __device__ __forceinline__ void precondition_lowrank(const WGTeam &tm, const QPV
     tm.sync();
     // wc = B u over the multi-entry rows
     const Rows rm(tm, v.lm);
-    {
-      int r = rm.g;
-      int i = r < R ? v.mrows[r] : 0;
-      int b = r < R ? v.arp[i] : 0, e = r < R ? v.arp[i + 1] : 0;
-      while (r < R) {
-        const int rn2 = r + rm.ng;
-        const int in = rn2 < R ? v.mrows[rn2] : 0;
-        const int bn = rn2 < R ? v.arp[in] : 0, en = rn2 < R ? v.arp[in + 1] : 0;
-        const double sr = sqrt(rho_i(i));
-        const double a = group_sum(seg_partial4<double>(v.aci, v.av, b, e, rm.lane, rm.L, u), rm.L);
-        if (rm.lane == 0) wc[r] = sr * a;
-        r = rn2; i = in; b = bn; e = en;
-      }
-    }
+    stream_rows<double>(v.arp, v.aci, v.av, u, rm.g, rm.ng, R, rm.lane, rm.L,
+                        [&](int r) __attribute__((always_inline)) { return v.mrows[r]; },
+                        [&](int i) __attribute__((always_inline)) { return v.iseq[i]; },
+                        [&](int r, int i, double a, unsigned char eq) __attribute__((always_inline)) {
+                          if (rm.lane == 0) wc[r] = sqrt(eq ? 1e3 * rho_bar : rho_bar) * a;
+                        });
     tm.sync();
     // w = S^-1 (B u), scattered to the rows of A with the factor R_m^1/2
     dense_rows_matvec(tm, Sinv, ldS, R, wc, [&](int r, double w) __attribute__((always_inline)) {
