@@ -178,11 +178,12 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
     if (lowrank) {
       for (int j = tm.tid; j < n; j += tm.nt) u[j] = Dl[j] * g[j];
       tm.sync();
-      for (int r = rm.g; r < R; r += rm.ng) {
-        const int i = multi[r];
-        const double a = group_sum(row_partial<double>(v.arp, v.aci, v.a64, i, rm.lane, rm.L, u), rm.L);
-        if (rm.lane == 0) wc[r] = rs * a;
-      }
+      stream_rows<double>(v.arp, v.aci, v.a64, u, rm.g, rm.ng, R, rm.lane, rm.L,
+                          [&](int r) __attribute__((always_inline)) { return multi[r]; },
+                          [&](int) __attribute__((always_inline)) { return 0; },
+                          [&](int r, int, double a, int) __attribute__((always_inline)) {
+                            if (rm.lane == 0) wc[r] = rs * a;
+                          });
       tm.sync();
       dense_solve_llt<double>(tm, s, S, r8, R, Sinv, wc);
       for (int r = tm.tid; r < R; r += tm.nt) wr[multi[r]] = rs * wc[r];
@@ -221,18 +222,17 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       const double a = group_sum(seg_partial4<double>(v.aci, v.a64, b, e, lane, L, tx), L);
       if (lane == 0) ry[i] = ai != 0.0 ? bi - a : 0.0;
     });
+    tm.sync();
+    // g = (-q - P t_x - A' t_y) + A' r_y / d: one pass over the rows of A'
+    // gathers both t_y and r_y
     rows_ahead2(v.prp, v.atrp, rn.g, rn.ng, n,
                 [&](int j, int pb, int pe, int ab, int ae) __attribute__((always_inline)) {
       const double qj = v.q64[j];
-      const double a = group_sum(seg_partial4<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx) +
-                                 seg_partial4<double>(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty), rn.L);
-      if (rn.lane == 0) rx[j] = -qj - a;
-    });
-    tm.sync();
-    rows_ahead(v.atrp, rn.g, rn.ng, n, [&](int j, int b, int e) __attribute__((always_inline)) {
-      const double rxj = rx[j];
-      const double a = group_sum(seg_partial4<double>(v.atci, v.at64, b, e, rn.lane, rn.L, ry), rn.L);
-      if (rn.lane == 0) g[j] = rxj + a * dinv_d;
+      const double2 at = seg_partial4x2(v.atci, v.at64, ab, ae, rn.lane, rn.L, ty, ry);
+      const double a = group_sum(seg_partial4<double>(v.pci, v.p64, pb, pe, rn.lane, rn.L, tx) + at.x,
+                                 rn.L);
+      const double ar = group_sum(at.y, rn.L);
+      if (rn.lane == 0) g[j] = (-qj - a) + ar * dinv_d;
     });
     tm.sync();
     msolve();

@@ -162,6 +162,43 @@ __device__ __forceinline__ A seg_partial4(const int *ci, const V *v, int b, int 
   return (s0 + s1) + (s2 + s3);
 }
 
+// seg_partial4 against two gathered vectors at once (one pass over the
+// entries): .x = sum v[k] x[ci[k]], .y = sum v[k] y[ci[k]], each in
+// seg_partial4's order.
+template <class V>
+__device__ __forceinline__ double2 seg_partial4x2(const int *ci, const V *v, int b, int e, int lane,
+                                                  int L, const double *x, const double *y) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  if (e <= b) return double2{0.0, 0.0};
+  const int last = (e - 1) & ~3;
+  for (int k = (b & ~3) + 4 * lane; k < e; k += 16 * L) {
+    int c[4][4];
+    V a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = min(k + 4 * L * u, last);
+      ld4(ci + kk, c[u]);
+      ld4(v + kk, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * L * u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = kk + q >= b && kk + q < e;
+        const int cq = ok ? c[u][q] : 0;
+        const double aq = ok ? double(a[u][q]) : 0.0;
+        const double tx = aq * x[cq], ty = aq * y[cq];
+        if (q == 0) { s0 += tx; t0 += ty; }
+        else if (q == 1) { s1 += tx; t1 += ty; }
+        else if (q == 2) { s2 += tx; t2 += ty; }
+        else { s3 += tx; t3 += ty; }
+      }
+    }
+  }
+  return double2{(s0 + s1) + (s2 + s3), (t0 + t1) + (t2 + t3)};
+}
+
 // sum over [b, e) of f(v[k], ci[k]) for the lanes of a group (not reduced),
 // with seg_partial4's chunked unconditional loads and summation order.
 template <class A, class V, class F>

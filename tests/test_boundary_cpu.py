@@ -119,5 +119,8 @@ def test_handle_functions_reject_null(pm):
     assert L.osqp_batch_solve(None) == 10
     assert L.osqp_update_vectors(None, None, None, None) == 10
     assert L.osqp_warm_start(None, None, None) == 10
+    assert L.osqp_batch_solve_graph_async(None) == 10
+    assert L.osqp_batch_autotune(None, 1, None) == 10
+    assert L.osqp_batch_set_shape(None, 256, 16) == 10
     L.osqp_cleanup(None)
     L.osqp_batch_cleanup(None)
