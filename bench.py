@@ -91,13 +91,17 @@ def algorithmic_bytes(qps, infos, value_bytes=4, check_every=25):
     return float(total)
 
 
+# the headers that hold device code (the kernels and what they include);
+# api.hip and server.h are host code
+KERNEL_SOURCES = ("dense.h", "kernels.h", "polish.h", "qp_layout.h", "solver_device.h", "team.h")
+
+
 def kernel_source_sha256() -> str:
-    """Hash of the kernel sources (csrc/*.h, csrc/*.hip), to tie a stored
-    counter measurement to the code it was taken on."""
-    import glob
+    """Hash of the device-code sources, to tie a stored counter measurement
+    to the kernels it was taken on (the launch shape is recorded beside it)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1711_08013_amd", "csrc")
-    files = sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip")))
+    files = [os.path.join(csrc, f) for f in KERNEL_SOURCES]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())

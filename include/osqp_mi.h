@@ -182,6 +182,20 @@ osqp_int osqp_update_vectors(osqp_solver *h, const osqp_float *q,
  * current iterate), z0 = A x0. */
 osqp_int osqp_warm_start(osqp_solver *h, const osqp_float *x, const osqp_float *y);
 
+/* Replace the values of P and/or A with the sparsity patterns kept (Section
+ * 6, matrices as parameters; the paper re-factors numerically and keeps the
+ * symbolic part).  P_upper_data: the P_nnz values of the upper triangle in
+ * the CSR order of the setup; A_data: the A_nnz values of A in its CSR order;
+ * NULL leaves that matrix unchanged.  The new data is unscaled: the modified
+ * Ruiz equilibration of Section 5.1 is recomputed on the device from it, the
+ * stored factor of the reduced matrix is recomputed at the next solve, and
+ * that solve is warm-started from the last solution (unscaled x, y).  P must
+ * stay positive semidefinite (not checked).  Blocks until done.
+ * OSQP_ERR_DIM when a count differs from the setup's, OSQP_ERR_DATA_NONFINITE
+ * for NaN/inf values. */
+osqp_int osqp_update_matrices(osqp_solver *h, const osqp_float *P_upper_data, osqp_int P_nnz,
+                              const osqp_float *A_data, osqp_int A_nnz);
+
 /* Copy the last solution (unscaled, FP64) to x (n) and y (m); either may be NULL. */
 osqp_int osqp_get_solution(const osqp_solver *h, osqp_float *x, osqp_float *y);
 osqp_int osqp_get_info(const osqp_solver *h, osqp_info *info);
@@ -244,6 +258,9 @@ osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *
                                    const osqp_float *l, const osqp_float *u);
 osqp_int osqp_batch_warm_start(osqp_batch *b, osqp_int i, const osqp_float *x,
                                const osqp_float *y);
+/* osqp_update_matrices for problem i of a batch. */
+osqp_int osqp_batch_update_matrices(osqp_batch *b, osqp_int i, const osqp_float *P_upper_data,
+                                    osqp_int P_nnz, const osqp_float *A_data, osqp_int A_nnz);
 /* Result of problem i: x (n_i), y (m_i) and info; any pointer may be NULL. */
 osqp_int osqp_batch_get(const osqp_batch *b, osqp_int i, osqp_float *x, osqp_float *y,
                         osqp_info *info);

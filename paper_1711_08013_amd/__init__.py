@@ -28,12 +28,14 @@ LINSYS = {"auto": 0, "pcg": 1, "dense": 2, "lowrank": 3}
 EXPORTS = [
     "osqp_set_default_settings", "osqp_error_string", "osqp_device_count",
     "osqp_device_info", "osqp_setup",
-    "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_get_solution",
+    "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_update_matrices",
+    "osqp_get_solution",
     "osqp_get_info", "osqp_cleanup", "osqp_batch_setup", "osqp_batch_solve",
     "osqp_batch_solve_async", "osqp_batch_solve_subset_async", "osqp_batch_sync",
     "osqp_batch_solve_graph_async", "osqp_batch_autotune", "osqp_batch_set_shape",
     "osqp_batch_reset",
-    "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_get",
+    "osqp_batch_update_vectors", "osqp_batch_warm_start", "osqp_batch_update_matrices",
+    "osqp_batch_get",
     "osqp_batch_last_kernel_ms", "osqp_batch_count", "osqp_batch_get_factor",
     "osqp_batch_cleanup", "osqp_server_create", "osqp_server_submit", "osqp_server_wait",
     "osqp_server_stats", "osqp_server_destroy",
@@ -252,6 +254,26 @@ class Batch:
         _check(lib().osqp_batch_update_vectors(self._h, i, _ptr(qa), _ptr(la), _ptr(ua)),
                "osqp_batch_update_vectors")
 
+    def update_matrices(self, i: int, P=None, A=None):
+        """New values of P (upper triangle) and/or A with the setup's patterns
+        (scipy sparse); the next solve rescales, refactors and warm-starts."""
+        import scipy.sparse as sp
+        k = self._keep[i]
+        pa = aa = None
+        if P is not None:
+            P = sp.csr_matrix(P)
+            if not (np.array_equal(P.indptr, k.Pp) and np.array_equal(P.indices, k.Pi)):
+                raise ValueError("P pattern differs from the setup's")
+            pa = np.ascontiguousarray(P.data, dtype=np.float64)
+        if A is not None:
+            A = sp.csr_matrix(A)
+            if not (np.array_equal(A.indptr, k.Ap) and np.array_equal(A.indices, k.Ai)):
+                raise ValueError("A pattern differs from the setup's")
+            aa = np.ascontiguousarray(A.data, dtype=np.float64)
+        _check(lib().osqp_batch_update_matrices(self._h, i, _ptr(pa), 0 if pa is None else pa.size,
+                                                _ptr(aa), 0 if aa is None else aa.size),
+               "osqp_batch_update_matrices")
+
     def warm_start(self, i: int, x=None, y=None):
         n, m = self.sizes[i]
         xa = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
@@ -358,6 +380,9 @@ class Solver(Batch):
 
     def warm_start(self, x=None, y=None):
         super().warm_start(0, x, y)
+
+    def update_matrices(self, P=None, A=None):
+        super().update_matrices(0, P, A)
 
     def result(self):
         return super().get(0)

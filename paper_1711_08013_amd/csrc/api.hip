@@ -140,6 +140,16 @@ struct osqp_batch {
   // host staging of the inputs that change through the parametric API
   std::vector<double> q_raw, l_raw, u_raw;
   std::vector<double> xws_h, yws_h;   // warm-start staging
+  // matrix updates: where each entry of the caller's CSR data lands in the
+  // packed device arrays (built from the device patterns on first use), and
+  // the staging of the new values
+  bool maps_built = false;
+  std::vector<int64_t> at_pos;          // per entry of A (packed order): index in A'
+  std::vector<int64_t> p_up, p_lo;      // per entry of P's upper triangle: index of (i,j), of (j,i) or -1
+  std::vector<int64_t> up_off;          // per QP: first entry of its upper triangle in p_up / p_lo
+  std::vector<int> up_cnt;              // per QP: entries of its upper triangle
+  std::vector<int> a_cnt;               // per QP: entries of A
+  std::vector<double> upd_a, upd_at, upd_p;
   std::vector<unsigned char> is_eq;
   // device
   char *arena = nullptr;
@@ -1331,6 +1341,143 @@ int update_vectors_impl(osqp_batch *b, int i, const double *q, const double *l, 
   return OSQP_OK;
 }
 
+int warm_start_impl(osqp_batch *b, int i, const double *x, const double *y, bool sync);
+
+// Positions of the caller's CSR entries in the packed arrays, from the
+// device patterns: A's entries go to A' in the counting-sort order of the
+// setup; P's upper-triangle entries to the full symmetric rows (row i's
+// entries with column >= i are row i of the upper triangle, in order; entry
+// (j, i), i < j, of full row j mirrors the next off-diagonal entry of upper
+// row i when the rows are taken in increasing j).
+template <class T>
+int build_pattern_maps(osqp_batch *b) {
+  const Batch<T> &B = batch_of<T>(b);
+  const int64_t sn = b->sum_n, sm = b->sum_m, na = b->nnz_a, np = b->nnz_p;
+  std::vector<int> a_rp(sm + b->nq), a_ci(na), at_rp(sn + b->nq), p_rp(sn + b->nq), p_ci(np);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  HIPCHK(hipMemcpy(a_rp.data(), B.a_rp, sizeof(int) * a_rp.size(), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(a_ci.data(), B.a_ci, sizeof(int) * na, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(at_rp.data(), B.at_rp, sizeof(int) * at_rp.size(), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(p_rp.data(), B.p_rp, sizeof(int) * p_rp.size(), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(p_ci.data(), B.p_ci, sizeof(int) * np, hipMemcpyDeviceToHost));
+  b->at_pos.assign(na, -1);
+  b->up_off.assign(b->nq, 0);
+  b->up_cnt.assign(b->nq, 0);
+  b->a_cnt.assign(b->nq, 0);
+  int64_t nup = 0;
+  for (int k = 0; k < b->nq; ++k) {
+    const QPDesc &d = b->desc[k];
+    const int *prp = &p_rp[d.p_rp], *pci = &p_ci[d.p_nz];
+    int cnt = 0;
+    for (int i = 0; i < d.n; ++i)
+      for (int e = prp[i]; e < prp[i + 1]; ++e) cnt += pci[e] >= i;
+    b->up_off[k] = nup;
+    b->up_cnt[k] = cnt;
+    nup += cnt;
+  }
+  b->p_up.assign(nup, -1);
+  b->p_lo.assign(nup, -1);
+  for (int k = 0; k < b->nq; ++k) {
+    const QPDesc &d = b->desc[k];
+    // A -> A'
+    const int *arp = &a_rp[d.a_rp], *aci = &a_ci[d.a_nz], *atrp = &at_rp[d.at_rp];
+    b->a_cnt[k] = arp[d.m];
+    std::vector<int> nxt(atrp, atrp + d.n);
+    for (int i = 0; i < d.m; ++i)
+      for (int e = arp[i]; e < arp[i + 1]; ++e) b->at_pos[d.a_nz + e] = d.at_nz + nxt[aci[e]]++;
+    // P upper -> full
+    const int *prp = &p_rp[d.p_rp], *pci = &p_ci[d.p_nz];
+    std::vector<int64_t> ub(d.n + 1, 0), oc(d.n, 0);
+    for (int i = 0; i < d.n; ++i) {
+      int c = 0;
+      bool diag = false;
+      for (int e = prp[i]; e < prp[i + 1]; ++e) {
+        c += pci[e] >= i;
+        diag |= pci[e] == i;
+      }
+      ub[i + 1] = ub[i] + c;
+      oc[i] = ub[i] + (diag ? 1 : 0);
+    }
+    int64_t *up = &b->p_up[b->up_off[k]], *lo = &b->p_lo[b->up_off[k]];
+    for (int i = 0; i < d.n; ++i) {
+      int64_t t = ub[i];
+      for (int e = prp[i]; e < prp[i + 1]; ++e) {
+        const int c = pci[e];
+        if (c >= i) up[t++] = d.p_nz + e;
+        else lo[oc[c]++] = d.p_nz + e;
+      }
+    }
+  }
+  b->maps_built = true;
+  return OSQP_OK;
+}
+
+// New values of P (upper triangle, in the setup's CSR order) and/or A (CSR
+// order), same patterns (Section 6, matrices as parameters): the raw copies
+// are replaced, the Ruiz scaling of Section 5.1 is recomputed on the device,
+// the stored factor is marked stale (refactored at the next solve) and the
+// next solve is warm-started from the last solution.
+template <class T>
+int update_matrices_impl(osqp_batch *b, int i, const double *P, int P_nnz, const double *A,
+                         int A_nnz) {
+  if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
+  if (!b->maps_built) {
+    const int rc = build_pattern_maps<T>(b);
+    if (rc) return rc;
+  }
+  const QPDesc &d = b->desc[i];
+  if (A && A_nnz != b->a_cnt[i]) return OSQP_ERR_DIM;
+  if (P && P_nnz != b->up_cnt[i]) return OSQP_ERR_DIM;
+  if (A)
+    for (int e = 0; e < A_nnz; ++e)
+      if (!std::isfinite(A[e])) return OSQP_ERR_DATA_NONFINITE;
+  if (P)
+    for (int e = 0; e < P_nnz; ++e)
+      if (!std::isfinite(P[e])) return OSQP_ERR_DATA_NONFINITE;
+  Batch<T> &B = batch_of<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (A && A_nnz > 0) {
+    b->upd_a.assign(A, A + A_nnz);
+    b->upd_at.assign(A_nnz, 0.0);
+    for (int e = 0; e < A_nnz; ++e) b->upd_at[b->at_pos[d.a_nz + e] - d.at_nz] = A[e];
+    HIPCHK(hipMemcpy((void *)(B.a_raw + d.a_nz), b->upd_a.data(), sizeof(double) * A_nnz,
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy((void *)(B.at_raw + d.at_nz), b->upd_at.data(), sizeof(double) * A_nnz,
+                     hipMemcpyHostToDevice));
+  }
+  if (P && P_nnz > 0) {
+    const int64_t *up = &b->p_up[b->up_off[i]], *lo = &b->p_lo[b->up_off[i]];
+    int64_t full = 0;
+    for (int e = 0; e < P_nnz; ++e) full = std::max(full, std::max(up[e], lo[e]) + 1 - d.p_nz);
+    b->upd_p.assign(full, 0.0);
+    for (int e = 0; e < P_nnz; ++e) {
+      b->upd_p[up[e] - d.p_nz] = P[e];
+      if (lo[e] >= 0) b->upd_p[lo[e] - d.p_nz] = P[e];
+    }
+    HIPCHK(hipMemcpy((void *)(B.p_raw + d.p_nz), b->upd_p.data(), sizeof(double) * full,
+                     hipMemcpyHostToDevice));
+  }
+  // rescale this QP from its raw data (a one-QP list), factor stale
+  if (!b->d_subset) {
+    if (hipMalloc(&b->d_subset, sizeof(int) * b->nq) != hipSuccess ||
+        hipMalloc(&b->d_subset_polish, sizeof(int) * b->nq) != hipSuccess)
+      return OSQP_ERR_ALLOC;
+  }
+  b->subset_h.assign(1, i);
+  HIPCHK(hipMemcpy(b->d_subset, b->subset_h.data(), sizeof(int), hipMemcpyHostToDevice));
+  B.set = b->dev_settings();
+  reset_counters_kernel<<<1, 64, 0, b->stream>>>(B.counter, 64, nullptr);
+  scale_wg_kernel<T><<<1, b->block, 0, b->stream>>>(B, b->d_subset, 1, 0);
+  HIPCHK(hipGetLastError());
+  static const double zero = 0.0;
+  HIPCHK(hipMemcpyAsync((void *)&B.st[i].factor_rho, &zero, sizeof(double), hipMemcpyHostToDevice,
+                        b->stream));
+  const int rc = warm_start_impl(b, i, nullptr, nullptr, false);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return OSQP_OK;
+}
+
 // Warm start of Section 6 on the batch's stream; the values are staged in
 // the batch's own host buffers (sync = false: as for update_vectors_impl).
 int warm_start_impl(osqp_batch *b, int i, const double *x, const double *y, bool sync) {
@@ -1372,6 +1519,22 @@ osqp_int osqp_batch_update_vectors(osqp_batch *b, osqp_int i, const osqp_float *
 osqp_int osqp_update_vectors(osqp_solver *h, const osqp_float *q, const osqp_float *l,
                              const osqp_float *u) {
   return osqp_batch_update_vectors(h, 0, q, l, u);
+}
+
+osqp_int osqp_batch_update_matrices(osqp_batch *b, osqp_int i, const osqp_float *P_upper_data,
+                                    osqp_int P_nnz, const osqp_float *A_data, osqp_int A_nnz) {
+  if (!b) return OSQP_ERR_NOT_SETUP;
+  try {
+    return b->fp64 ? update_matrices_impl<double>(b, i, P_upper_data, P_nnz, A_data, A_nnz)
+                   : update_matrices_impl<float>(b, i, P_upper_data, P_nnz, A_data, A_nnz);
+  } catch (...) {
+    return OSQP_ERR_ALLOC;
+  }
+}
+
+osqp_int osqp_update_matrices(osqp_solver *h, const osqp_float *P_upper_data, osqp_int P_nnz,
+                              const osqp_float *A_data, osqp_int A_nnz) {
+  return osqp_batch_update_matrices(h, 0, P_upper_data, P_nnz, A_data, A_nnz);
 }
 
 osqp_int osqp_batch_warm_start(osqp_batch *b, osqp_int i, const osqp_float *x,

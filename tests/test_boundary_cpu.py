@@ -122,5 +122,7 @@ def test_handle_functions_reject_null(pm):
     assert L.osqp_batch_solve_graph_async(None) == 10
     assert L.osqp_batch_autotune(None, 1, None) == 10
     assert L.osqp_batch_set_shape(None, 256, 16) == 10
+    assert L.osqp_update_matrices(None, None, 0, None, 0) == 10
+    assert L.osqp_batch_update_matrices(None, 0, None, 0, None, 0) == 10
     L.osqp_cleanup(None)
     L.osqp_batch_cleanup(None)
