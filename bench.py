@@ -174,6 +174,58 @@ def fp64_plain(pm, qps, budget_s: float, extra: dict):
             "p99_latency_ms": float(np.percentile(times, 99) * 1e3)}
 
 
+def parametric_leg(pm):
+    """Parametric re-solves (Section 6) on one QP each: a Lasso path of twelve
+    lambda values (q updated, iterate kept) against cold solves, and an MPC
+    closed loop of twenty steps (initial-state bounds updated); iterations and
+    device time per re-solve."""
+    out = {}
+    base = qpgen.lasso(qpgen.rng_for(2, 11), 200, 2000, density=0.05, lam_frac=1.0)
+    nf = 200
+    fracs = np.geomspace(0.9, 0.05, 12)
+    warm = pm.Solver(base, precision="fp32")
+    warm.solve()
+    it_w = it_c = 0
+    ms_w = ms_c = 0.0
+    for f in fracs:
+        q = base.q.copy()
+        q[-nf:] = f * base.lam
+        warm.update_vectors(q=q)
+        warm.solve()
+        it_w += warm.result()[2]["iter"]
+        ms_w += warm.last_kernel_ms()
+        cold = pm.Solver(qpgen.QP(base.P, q, base.A, base.l, base.u), precision="fp32")
+        cold.solve()
+        it_c += cold.result()[2]["iter"]
+        ms_c += cold.last_kernel_ms()
+        cold.close()
+    warm.close()
+    out["lasso_path"] = {"problem": "Lasso 2000 x 200 at 5%, 12 lambda values in [0.05, 0.9] lambda_max",
+                         "iters_warm": it_w, "iters_cold": it_c,
+                         "kernel_ms_warm": round(ms_w, 3), "kernel_ms_cold": round(ms_c, 3)}
+    rng = qpgen.rng_for(3, 901)
+    plant = qpgen.mpc_plant(rng)
+    Ad, B = plant[0], plant[1]
+    nx, nu, T = 20, 10, 10
+    x = rng.uniform(-1.0, 1.0, nx)
+    s = pm.Solver(qpgen.mpc(rng, T=T, plant=plant, x_init=x), precision="fp32")
+    its, ms = [], []
+    for _ in range(20):
+        s.solve()
+        xs, _, info = s.result()
+        its.append(info["iter"])
+        ms.append(s.last_kernel_ms())
+        x = Ad @ x + B @ xs[nx * (T + 1): nx * (T + 1) + nu]
+        nq = qpgen.mpc(rng, T=T, plant=plant, x_init=x)
+        s.update_vectors(l=nq.l, u=nq.u)
+    s.close()
+    out["mpc_closed_loop"] = {"problem": "MPC nx=20, nu=10, T=10, 20 steps",
+                              "iters_mean": float(np.mean(its)),
+                              "kernel_ms_p50": round(float(np.percentile(ms, 50)), 3),
+                              "kernel_ms_p99": round(float(np.percentile(ms, 99)), 3)}
+    return out
+
+
 def serving_leg(pm, n_req: int, rate: float, n_max_random: int, gen_budget_s: float):
     """Continuous-batching server under a Poisson stream mixing the random-QP,
     MPC and portfolio generators (repeats of an MPC plant or a portfolio
@@ -233,6 +285,7 @@ def main():
     ap.add_argument("--serving-nmax", type=int, default=1000,
                     help="largest random-QP n in the serving mix")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-parametric", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the setup's launch shape (no tuning before the timed steps)")
     ap.add_argument("--shape", default=None,
@@ -325,6 +378,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(qps, args.cpu_budget, extra)
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
     batch.close()
+    if not args.no_parametric:
+        print("# parametric re-solves", file=sys.stderr, flush=True)
+        out["parametric"] = parametric_leg(pm)
     if not args.no_serving:
         print("# serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_leg(pm, args.serving_requests, args.serving_rate,
