@@ -286,6 +286,7 @@ def main():
                     help="largest random-QP n in the serving mix")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-parametric", action="store_true")
+    ap.add_argument("--no-high-accuracy", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the setup's launch shape (no tuning before the timed steps)")
     ap.add_argument("--shape", default=None,
@@ -378,6 +379,22 @@ def main():
         out["cpu_baseline"] = cpu_baseline(qps, args.cpu_budget, extra)
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
     batch.close()
+    if not args.no_high_accuracy:
+        # the same batch at the paper's high-accuracy setting, eps = 1e-5
+        print("# high accuracy", file=sys.stderr, flush=True)
+        hb = pm.Batch(qps, precision="fp32", eps_abs=1e-5, eps_rel=1e-5, max_iter=20000, **extra)
+        if shape:
+            hb.set_shape(*shape)
+        hb.reset()
+        t0 = time.perf_counter()
+        hb.solve()
+        hs = time.perf_counter() - t0
+        hinf = [hb.get(i)[2] for i in range(len(qps))]
+        hsolved = sum(1 for i in hinf if i["status_name"] == "solved")
+        out["high_accuracy"] = {"eps": 1e-5, "solved": hsolved, "qps_per_s": round(hsolved / hs, 2),
+                                "batch_ms": round(hs * 1e3, 3),
+                                "mean_iter": round(float(np.mean([i["iter"] for i in hinf])), 1)}
+        hb.close()
     if not args.no_parametric:
         print("# parametric re-solves", file=sys.stderr, flush=True)
         out["parametric"] = parametric_leg(pm)
