@@ -902,13 +902,16 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     } else {
       start_pass(v.s64, v.xt);
     }
-    // the dense preconditioner is a factor of K itself: it is applied only
-    // while the residual misses the tolerance (the PCG iterates are the same)
+    // the dense preconditioner is a factor of K itself: one PCG step with it
+    // is the exact solve
     bool dense_skip = false;
     if constexpr (std::is_same<Team, WGTeam>::value) {
       if (use_dense) {
         tm.template reduce<0, 1>(red + 1);
-        dense_skip = bnorm >= 0.0 && red[1] <= pcg_tol(bnorm);
+        // with an exact factor every ADMM step takes its linear solve, as the
+        // direct method does: skipping it while the residual is under the
+        // inner tolerance ends at another eps-solution than the direct method
+        dense_skip = false;
         if (direct) {
           if (!dense_skip) precondition_lowrank(tm, v, rho_bar, stage, true, true);
         } else if (!dense_skip) {
@@ -933,7 +936,11 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     // residual before the first check
     const double tol = pcg_tol(bnorm);
     int it = (direct && !dense_skip) ? 1 : 0;
-    while (!direct && !dense_skip && rinf > tol && it < set.pcg_max_iter) {
+    // with the exact factor the first step is taken even below the inner
+    // tolerance (unless the residual is exactly zero)
+    const bool forced0 = use_dense && !(rinf > tol);
+    while (!direct && !dense_skip && (rinf > tol || (forced0 && it == 0 && rinf > 0.0)) &&
+           it < set.pcg_max_iter) {
       // t = R A p ; w = P p + sigma p + A' t ; p'w
       auto kprod = [&](const T *p_src, T *t_dst, const T *t_src) __attribute__((always_inline)) {
         for_a_rows(tm, v, rm, [&](int i, int b, int e, int lane, int L) __attribute__((always_inline)) {
@@ -965,7 +972,12 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       }
       tm.template reduce<1, 0>(red);
       const double pw = red[0];
-      if (!(pw > 0.0) || !isfinite(pw)) { bad |= 1; break; }
+      if (!(pw > 0.0) || !isfinite(pw)) {
+        // a step below the inner tolerance whose curvature underflows is
+        // negligible: x~ stays (not a breakdown)
+        if (!(forced0 && it == 0) || !isfinite(pw)) bad |= 1;
+        break;
+      }
       const double a_d = rz / pw;
       const T a_step = T(a_d);
       red[0] = 0.0; red[1] = 0.0;
@@ -1134,6 +1146,9 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     drs = chk[12]; dnorm = fmax(chk[13], fmax(chk[14], chk[15]));
     have_check = true;
     lap(c_check);
+    // non-finite iterates: the maxima above drop NaN, the sums keep it; stop
+    // as unsolved rather than read the dropped terms as converged
+    if (!isfinite(chk[0]) || !isfinite(chk[1])) { bad |= 2; status = 6; break; }
     if (res_prim <= eps_prim && res_dual <= eps_dual) { status = 1; break; }
     // primal infeasibility (Section 5.1, strict-sign reading)
     {

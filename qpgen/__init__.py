@@ -292,6 +292,36 @@ def huber(rng: np.random.Generator, n_features: int, m_data: int | None = None,
 # --------------------------------------------------------------------------
 # Small structured instances used by the closed-form checks
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# Appendix A.7: support vector machine
+# --------------------------------------------------------------------------
+def svm(rng: np.random.Generator, n_features: int, m_data: int | None = None,
+        density: float = 0.15, lam: float = 1.0) -> QP:
+    """Variables (x, t); min x'x + lam 1't  s.t.  t >= diag(b) A x + 1, t >= 0.
+    b = +1 on the first m/2 points, -1 on the rest; the entries of A are
+    N(+1/n, 1/n) on the first half and N(-1/n, 1/n) on the second, 15% dense.
+    Readings (not stated in the appendix): m = 100 n as for the other fitting
+    problems, lam = 1."""
+    nf = n_features
+    md = 100 * nf if m_data is None else m_data
+    half = md // 2
+    mask = rng.random((md, nf)) < density
+    mean = np.where(np.arange(md)[:, None] < half, 1.0 / nf, -1.0 / nf)
+    vals = mean + math.sqrt(1.0 / nf) * rng.standard_normal((md, nf))
+    Ad = sp.csr_matrix(np.where(mask, vals, 0.0))
+    b = np.where(np.arange(md) < half, 1.0, -1.0)
+    n = nf + md
+    Pfull = sp.block_diag([2.0 * sp.identity(nf), sp.csr_matrix((md, md))], format="csr")
+    q = np.concatenate([np.zeros(nf), lam * np.ones(md)])
+    A = sp.vstack([
+        sp.hstack([-sp.diags(b) @ Ad, sp.identity(md)]),
+        sp.hstack([sp.csr_matrix((md, nf)), sp.identity(md)]),
+    ])
+    l = np.concatenate([np.ones(md), np.zeros(md)])
+    u = np.full(2 * md, np.inf)
+    return QP(_upper(Pfull), q, _csr(A), l, u, name=f"svm(nf={nf},md={md})")
+
+
 def box_qp(d: np.ndarray, q: np.ndarray, l: np.ndarray, u: np.ndarray) -> QP:
     """min 1/2 x'diag(d)x + q'x  s.t.  l <= x <= u  (A = I)."""
     n = d.size
