@@ -35,6 +35,9 @@ WORKLOADS = {
                            "k=n/10, F 50% dense", {"polish": 1}),
     "mpc": (3, 4096, "batched linear MPC, 4096 QPs, nx=20, nu=10, T in [5,20]", {}),
 }
+# launch shape (workgroup size : lane divisor) applied before the timed steps
+# unless --autotune is given: the shape the tuner kept for the workload
+DEFAULT_SHAPES = {"portfolio": "512:32", "mpc": "256:32"}
 
 
 def build_workload(name: str, count: int | None):
@@ -287,10 +290,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-parametric", action="store_true")
     ap.add_argument("--no-high-accuracy", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the setup's launch shape (no tuning before the timed steps)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch shapes before the timed steps and keep the fastest")
     ap.add_argument("--shape", default=None,
-                    help="BLOCK:LANE_DIV launch shape to apply instead of tuning")
+                    help="BLOCK:LANE_DIV launch shape for the timed steps (default: the "
+                         "workload's entry in DEFAULT_SHAPES; 'setup' keeps the setup's shape)")
     ap.add_argument("--graph", action="store_true",
                     help="solve through the replayable graph of the solve launches")
     args = ap.parse_args()
@@ -311,15 +315,16 @@ def main():
     setup_s = time.perf_counter() - t0
     print(f"# setup {setup_s:.2f} s", file=sys.stderr, flush=True)
     tuning = None
-    if args.shape:
-        blk, div = (int(v) for v in args.shape.split(":"))
-        batch.set_shape(blk, div)
-        tuning = {"block_size": blk, "lane_div": div, "applied": True}
-    elif not args.no_autotune:
+    shape_arg = args.shape if args.shape else DEFAULT_SHAPES.get(args.workload, "setup")
+    if args.autotune:
         t0 = time.perf_counter()
         tuning = batch.autotune(reps=1)
         tuning["tune_s"] = round(time.perf_counter() - t0, 3)
         print(f"# autotune {tuning}", file=sys.stderr, flush=True)
+    elif shape_arg != "setup":
+        blk, div = (int(v) for v in shape_arg.split(":"))
+        batch.set_shape(blk, div)
+        tuning = {"block_size": blk, "lane_div": div, "applied": True}
 
     def step():
         batch.reset()
