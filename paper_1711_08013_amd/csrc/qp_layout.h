@@ -99,8 +99,8 @@ struct Batch {
   T *dmat;
   T *dws;
   long long dws_stride;
-  // low-rank path (FP64): per-QP blocks [Delta^-1 | u | S | S-block
-  // inverses | w (compact) | w (by row)] and per-workgroup G scratch
+  // low-rank path (FP64): per-QP blocks [Delta^-1 | u | S^-1 | w (compact) |
+  // w (by row)] and per-workgroup scratch (G, then the inverse's panels)
   double *lmat;
   double *lws;
   long long lws_stride;
