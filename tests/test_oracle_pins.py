@@ -512,3 +512,59 @@ def test_no_false_primal_infeasibility_on_duplicate_equalities(oracle_lib):
     r = oracle_lib.solve(qp, x_ws=[1.0], y_ws=[3.0, -2.0], max_iter=25, eps_abs=1e-14,
                          eps_rel=1e-14, scaling_iters=0, adaptive_rho=0)
     assert r.status != "primal_infeasible"
+
+
+# ------------------------------------------- appendix fitting problems, restated
+def test_huber_qp_equals_huber_loss_minimum(oracle_lib):
+    """Appendix Huber fitting: eliminating (u, r, s) from the QP leaves the sum
+    of Huber penalties of the residuals Ax - b (quadratic inside M, linear with
+    slope 2M outside).  That smooth unconstrained problem is minimised here by
+    scipy's L-BFGS on the data block alone; the oracle's optimal objective and
+    x-part must match it."""
+    from scipy.optimize import minimize
+    nf, md, M = 6, 120, 1.0
+    qp = qpgen.huber(qpgen.rng_for(7, 31), nf, m_data=md, M=M)
+    Ad = qp.A[:md, :nf].toarray()
+    b = qp.l[:md]
+
+    def f(x):
+        e = Ad @ x - b
+        a = np.abs(e)
+        val = np.where(a <= M, e * e, 2.0 * M * a - M * M).sum()
+        g = Ad.T @ np.where(a <= M, 2.0 * e, 2.0 * M * np.sign(e))
+        return val, g
+
+    ref = minimize(f, np.zeros(nf), jac=True, method="L-BFGS-B",
+                   options={"ftol": 1e-15, "gtol": 1e-11, "maxiter": 10000})
+    r = oracle_lib.solve(qp, eps_abs=1e-9, eps_rel=1e-9, max_iter=200000, polish=1)
+    assert r.status == "solved"
+    assert abs(r.obj_val - ref.fun) <= 1e-7 * max(1.0, abs(ref.fun)), (r.obj_val, ref.fun)
+    assert np.allclose(r.x[:nf], ref.x, atol=1e-5)
+
+
+def test_svm_qp_equals_hinge_loss_minimum(oracle_lib):
+    """Appendix SVM: with t eliminated the QP is x'x + lam sum max(0, 1 + b_i a_i'x),
+    i.e. half of it is the soft-margin linear SVM 0.5 w'w + C sum hinge(y_i a_i'w)
+    with C = lam / 2 and labels y = -b, without an intercept.  scikit-learn's
+    liblinear (dual coordinate descent) solves that; its optimum, doubled, must
+    equal the oracle's objective, and the weights must agree."""
+    from sklearn.svm import LinearSVC
+    nf, md, lam = 5, 200, 1.0
+    qp = qpgen.svm(qpgen.rng_for(7, 41), nf, m_data=md, lam=lam)
+    Ab = -qp.A[:md, :nf].toarray()            # rows b_i a_i'
+    b = np.where(np.arange(md) < md // 2, 1.0, -1.0)
+    Ad = Ab * b[:, None]
+    clf = LinearSVC(C=lam / 2.0, loss="hinge", dual=True, fit_intercept=False,
+                    tol=1e-12, max_iter=1000000)
+    clf.fit(Ad, -b)
+    w = clf.coef_.ravel()
+
+    def obj(x):
+        return x @ x + lam * np.maximum(0.0, 1.0 + Ab @ x).sum()
+
+    r = oracle_lib.solve(qp, eps_abs=1e-9, eps_rel=1e-9, max_iter=200000, polish=1)
+    assert r.status == "solved"
+    f_ref = obj(w)
+    assert abs(r.obj_val - f_ref) <= 1e-6 * max(1.0, abs(f_ref)), (r.obj_val, f_ref)
+    assert abs(obj(r.x[:nf]) - r.obj_val) <= 1e-7 * max(1.0, abs(f_ref))
+    assert np.allclose(r.x[:nf], w, atol=1e-4)
