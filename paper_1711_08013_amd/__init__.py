@@ -152,12 +152,23 @@ def _ptr(a) -> ctypes.c_void_p:
     return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
 
 
+def _canonical_csr(M):
+    """CSR copy with duplicates summed and each row's columns sorted (the C ABI
+    requires strictly increasing columns); explicit zeros are kept, since
+    they belong to the pattern that later value updates refer to."""
+    import scipy.sparse as sp
+    C = sp.csr_matrix(M, copy=True)
+    C.sum_duplicates()
+    C.sort_indices()
+    return C
+
+
 class _Keep:
     """Typed contiguous copies of one QP's arrays, kept alive during a call."""
 
     def __init__(self, qp):
-        P = qp.P.tocsr()
-        A = qp.A.tocsr()
+        P = _canonical_csr(qp.P)
+        A = _canonical_csr(qp.A)
         self.n, self.m = int(P.shape[0]), int(A.shape[0])
         self.Pp = np.ascontiguousarray(P.indptr, dtype=np.int32)
         self.Pi = np.ascontiguousarray(P.indices, dtype=np.int32)
@@ -206,6 +217,18 @@ class Batch:
     def __len__(self):
         return len(self._keep)
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def _index(self, i: int) -> int:
+        if not 0 <= i < len(self._keep):
+            raise IndexError(f"problem index {i} outside 0..{len(self._keep) - 1}")
+        return i
+
     def solve(self):
         _check(lib().osqp_batch_solve(self._h), "osqp_batch_solve")
 
@@ -244,7 +267,7 @@ class Batch:
         _check(lib().osqp_batch_reset(self._h), "osqp_batch_reset")
 
     def update_vectors(self, i: int, q=None, l=None, u=None):
-        n, m = self.sizes[i]
+        n, m = self.sizes[self._index(i)]
         qa = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
         la = None if l is None else np.ascontiguousarray(l, dtype=np.float64)
         ua = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
@@ -257,16 +280,15 @@ class Batch:
     def update_matrices(self, i: int, P=None, A=None):
         """New values of P (upper triangle) and/or A with the setup's patterns
         (scipy sparse); the next solve rescales, refactors and warm-starts."""
-        import scipy.sparse as sp
-        k = self._keep[i]
+        k = self._keep[self._index(i)]
         pa = aa = None
         if P is not None:
-            P = sp.csr_matrix(P)
+            P = _canonical_csr(P)
             if not (np.array_equal(P.indptr, k.Pp) and np.array_equal(P.indices, k.Pi)):
                 raise ValueError("P pattern differs from the setup's")
             pa = np.ascontiguousarray(P.data, dtype=np.float64)
         if A is not None:
-            A = sp.csr_matrix(A)
+            A = _canonical_csr(A)
             if not (np.array_equal(A.indptr, k.Ap) and np.array_equal(A.indices, k.Ai)):
                 raise ValueError("A pattern differs from the setup's")
             aa = np.ascontiguousarray(A.data, dtype=np.float64)
@@ -275,7 +297,7 @@ class Batch:
                "osqp_batch_update_matrices")
 
     def warm_start(self, i: int, x=None, y=None):
-        n, m = self.sizes[i]
+        n, m = self.sizes[self._index(i)]
         xa = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
         ya = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
         if (xa is not None and xa.size != n) or (ya is not None and ya.size != m):
@@ -284,7 +306,7 @@ class Batch:
                "osqp_batch_warm_start")
 
     def get(self, i: int):
-        n, m = self.sizes[i]
+        n, m = self.sizes[self._index(i)]
         x = np.zeros(n)
         y = np.zeros(max(m, 1))
         info = _Info()
@@ -294,7 +316,7 @@ class Batch:
 
     def factor(self, i: int):
         """Dense Cholesky factor L (n x n, lower) of problem i's reduced matrix."""
-        n, _ = self.sizes[i]
+        n, _ = self.sizes[self._index(i)]
         L = np.zeros((n, n))
         _check(lib().osqp_batch_get_factor(self._h, i, _ptr(L)), "osqp_batch_get_factor")
         return L
@@ -341,13 +363,14 @@ class Server:
         return t.value
 
     def wait(self, ticket: int):
-        n, m = self._sizes.pop(ticket)
+        n, m = self._sizes[ticket]
         x = np.zeros(n)
         y = np.zeros(max(m, 1))
         info = _Info()
         lat = ctypes.c_double(0.0)
         _check(lib().osqp_server_wait(self._h, ctypes.c_uint64(ticket), _ptr(x), _ptr(y),
                                       ctypes.byref(info), ctypes.byref(lat)), "osqp_server_wait")
+        del self._sizes[ticket]
         return x, y[:m], _info_dict(info), lat.value
 
     def stats(self) -> dict:
@@ -361,6 +384,13 @@ class Server:
         if getattr(self, "_h", None):
             lib().osqp_server_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

@@ -126,3 +126,24 @@ def test_handle_functions_reject_null(pm):
     assert L.osqp_batch_update_matrices(None, 0, None, 0, None, 0) == 10
     L.osqp_cleanup(None)
     L.osqp_batch_cleanup(None)
+
+
+def test_binding_canonicalises_csr_input(pm):
+    """The binding hands the C ABI sorted, duplicate-free rows (which its
+    validation requires) without dropping explicit zeros of the pattern."""
+    # row 0 given with columns out of order and a duplicate, row 1 with an
+    # explicit zero
+    indptr = np.array([0, 3, 5])
+    indices = np.array([2, 0, 2, 1, 2])
+    data = np.array([1.0, 2.0, 3.0, 0.0, 5.0])
+    M = sp.csr_matrix((data, indices, indptr), shape=(2, 3))
+    C = pm._canonical_csr(M)
+    assert C.indptr.tolist() == [0, 2, 4]
+    assert C.indices.tolist() == [0, 2, 1, 2]
+    assert C.data.tolist() == [2.0, 4.0, 0.0, 5.0]
+    # the input is left as it was
+    assert M.indices.tolist() == [2, 0, 2, 1, 2]
+    P = sp.csr_matrix((np.array([1.0, 0.5, 2.0]), np.array([1, 0, 1]), np.array([0, 2, 3])),
+                      shape=(2, 2))
+    k = pm._Keep(QP(P, np.zeros(2), sp.csr_matrix(np.eye(2)), -np.ones(2), np.ones(2)))
+    assert k.Pi.tolist() == [0, 1, 1] and k.Px.tolist() == [0.5, 1.0, 2.0]
