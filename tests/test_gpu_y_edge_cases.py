@@ -1,0 +1,150 @@
+"""Degenerate and edge inputs on the GPU through the C ABI, against closed
+forms and the oracle: a scalar QP, no constraints at all (m = 0), A = I
+(no multi-entry rows, so the dense factor has no rank-k part), a linear
+program (P = 0), and rows of A that are empty or free (infinite bounds on
+both sides), which must not change the solution."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import qpgen
+from qpgen import QP
+from tests import gpu_common as gc
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp64", "fp32"]
+# tolerances of the tight solves: the FP32 path is held to the paper's
+# high-accuracy setting, the FP64 path one decade further
+EPS = {"fp64": 1e-6, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_1711_08013_amd as pm
+    assert pm.device_count() > 0, "no HIP device"
+    return pm
+
+
+def _qp(P, q, A, l, u, name):
+    P = sp.csr_matrix(np.triu(np.atleast_2d(np.asarray(P, float))))
+    A = sp.csr_matrix(np.asarray(A, float).reshape(len(l), -1))
+    return QP(P, np.asarray(q, float), A, np.asarray(l, float), np.asarray(u, float), name=name)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_scalar_qp(pm, precision):
+    """n = m = 1: min x^2 - 4x on [-1, 1] -> x = 1, y = 2 (bound active)."""
+    qp = _qp([[2.0]], [-4.0], [[1.0]], [-1.0], [1.0], "scalar")
+    print(f"scalar {precision}", flush=True)
+    e = EPS[precision]
+    x, y, info = pm.solve(qp, precision=precision, eps_abs=e, eps_rel=e)
+    gc.compare(qp, x, y, info, oracle.solve(qp, eps_abs=e, eps_rel=e), eps_abs=e, eps_rel=e)
+    assert abs(x[0] - 1.0) <= 1e-4 and abs(y[0] - 2.0) <= 1e-3
+    assert abs(info["obj_val"] + 3.0) <= 1e-4
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_no_constraints(pm, precision):
+    """m = 0: x = -P^-1 q, an empty dual."""
+    rng = np.random.default_rng(11)
+    n = 12
+    M = rng.standard_normal((n, n))
+    P = M @ M.T + np.eye(n)
+    q = rng.standard_normal(n)
+    qp = QP(sp.csr_matrix(np.triu(P)), q, sp.csr_matrix((0, n)), np.zeros(0), np.zeros(0),
+            name="m=0")
+    print(f"m=0 {precision}", flush=True)
+    e = EPS[precision]
+    x, y, info = pm.solve(qp, precision=precision, eps_abs=e, eps_rel=e)
+    assert info["status_name"] == "solved" and y.size == 0
+    xs = -np.linalg.solve(P, q)
+    assert np.allclose(x, xs, atol=1e-4 * max(1.0, np.abs(xs).max()))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_identity_constraints(pm, precision):
+    """A = I, P diagonal: x = clip(-q/d, l, u); no row of A has two entries."""
+    rng = np.random.default_rng(12)
+    n = 40
+    d = rng.uniform(0.1, 10.0, n)
+    q = 3 * rng.standard_normal(n)
+    l, u = -rng.random(n), rng.random(n)
+    qp = qpgen.box_qp(d, q, l, u)
+    print(f"A=I {precision}", flush=True)
+    e = EPS[precision]
+    x, y, info = pm.solve(qp, precision=precision, eps_abs=e, eps_rel=e)
+    gc.compare(qp, x, y, info, oracle.solve(qp, eps_abs=e, eps_rel=e), eps_abs=e, eps_rel=e)
+    assert np.allclose(x, np.clip(-q / d, l, u), atol=1e-4)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_linear_program(pm, precision):
+    """P = 0, A = I, finite box: x_i = l_i where q_i > 0, else u_i."""
+    rng = np.random.default_rng(13)
+    n = 20
+    q = rng.standard_normal(n)
+    l, u = -rng.random(n) - 0.1, rng.random(n) + 0.1
+    qp = QP(sp.csr_matrix((n, n)), q, sp.identity(n, format="csr"), l, u, name="box LP")
+    print(f"LP {precision}", flush=True)
+    e = EPS[precision]
+    kw = dict(eps_abs=e, eps_rel=e, max_iter=50000)
+    x, y, info = pm.solve(qp, precision=precision, **kw)
+    gc.compare(qp, x, y, info, oracle.solve(qp, **kw), eps_abs=e, eps_rel=e)
+    xs = np.where(q > 0, l, u)
+    assert np.allclose(x, xs, atol=1e-3)
+    assert abs(info["obj_val"] - q @ xs) <= 1e-3 * max(1.0, abs(q @ xs))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_empty_and_free_rows_change_nothing(pm, precision):
+    """Rows without entries (l <= 0 <= u) and rows with infinite bounds on
+    both sides added to a random QP: same status, and the objective of the
+    base problem's solution."""
+    base = qpgen.config_instance(1, 5)
+    rng = np.random.default_rng(14)
+    k_free = 3
+    F = sp.csr_matrix(rng.standard_normal((k_free, base.n)))
+    E = sp.csr_matrix((2, base.n))
+    A = sp.vstack([base.A, E, F], format="csr")
+    l = np.concatenate([base.l, [-1.0, 0.0], -np.inf * np.ones(k_free)])
+    u = np.concatenate([base.u, [1.0, 0.0], np.inf * np.ones(k_free)])
+    qp = QP(base.P, base.q, A, l, u, name="random + empty + free rows")
+    print(f"empty/free rows {precision}", flush=True)
+    e = EPS[precision]
+    kw = dict(eps_abs=e, eps_rel=e, max_iter=50000)
+    xb, yb, ib = pm.solve(base, precision=precision, **kw)
+    x, y, info = pm.solve(qp, precision=precision, **kw)
+    gc.compare(qp, x, y, info, oracle.solve(qp, **kw), eps_abs=e, eps_rel=e)
+    assert info["status_name"] == ib["status_name"] == "solved"
+    assert abs(info["obj_val"] - ib["obj_val"]) <= 1e-4 * max(1.0, abs(ib["obj_val"]))
+    assert np.allclose(y[base.m:], 0.0, atol=1e-6)
+
+
+def test_batch_of_degenerate_and_regular_qps(pm):
+    """Scalar, m = 0, A = I and LP instances in one batch with regular QPs:
+    each result is bitwise the one of its solve alone (one QP per
+    workgroup, fixed reduction order)."""
+    rng = np.random.default_rng(15)
+    n = 6
+    M = rng.standard_normal((n, n))
+    odd = [
+        _qp([[2.0]], [-4.0], [[1.0]], [-1.0], [1.0], "scalar"),
+        QP(sp.csr_matrix(np.triu(M @ M.T + np.eye(n))), rng.standard_normal(n),
+           sp.csr_matrix((0, n)), np.zeros(0), np.zeros(0), name="m=0"),
+        qpgen.box_qp(rng.uniform(0.1, 2.0, 9), rng.standard_normal(9), -np.ones(9), np.ones(9)),
+    ]
+    regular = [qpgen.config_instance(1, i) for i in range(4)]
+    qps = regular[:2] + odd + regular[2:]
+    print("degenerate batch", flush=True)
+    b = pm.Batch(qps, precision="fp32")
+    b.solve()
+    mixed = [b.get(i) for i in range(len(qps))]
+    b.close()
+    for qp, (x, y, info) in zip(qps, mixed):
+        xa, ya, ia = pm.solve(qp, precision="fp32")
+        assert info["status_name"] == ia["status_name"] == "solved", qp.name
+        assert np.array_equal(x, xa) and np.array_equal(y, ya), qp.name
