@@ -1,0 +1,104 @@
+"""Host build of the library with its kernels run on the CPU (test
+infrastructure only; the product library is the gfx950 build of
+paper_1711_08013_amd/build.py).
+
+The library source is compiled as plain C++ against the stand-in runtime in
+tests/simt/include/hip/hip_runtime.h.  Two mechanical edits are made to a
+copy of it: each triple-chevron launch becomes a call of simt::launch with
+the kernel call in a lambda, and the server (which launches from its own
+thread) is left out.  The build uses the host address sanitizer, so every
+device-memory access of the kernels is bounds-checked against the
+allocation it belongs to."""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_1711_08013_amd", "csrc")
+OUT_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(OUT_DIR, "libosqp_simt.so")
+CLANG = os.environ.get("SIMT_CXX", "/opt/rocm/llvm/bin/clang++")
+SEPARATE_ARRAYS = os.environ.get("SIMT_ONE_ARENA", "") == ""
+
+
+def asan_runtime() -> str:
+    """Path of the sanitizer runtime to preload into a Python process that
+    loads the library."""
+    out = subprocess.run([CLANG, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True, check=True).stdout.strip()
+    if not os.path.isabs(out) or not os.path.exists(out):
+        raise RuntimeError("address-sanitizer runtime not found next to " + CLANG)
+    return out
+
+
+def _split_top(s: str) -> list[str]:
+    parts, depth, cur = [], 0, []
+    for ch in s:
+        if ch in "([{":
+            depth += 1
+        elif ch in ")]}":
+            depth -= 1
+        if ch == "," and depth == 0:
+            parts.append("".join(cur).strip())
+            cur = []
+        else:
+            cur.append(ch)
+    parts.append("".join(cur).strip())
+    return parts
+
+
+_LAUNCH = re.compile(r"([A-Za-z_]\w*(?:<[^<>;()]*>)?)<<<(.*?)>>>\((.*?)\);", re.S)
+
+
+def translate(src: str) -> str:
+    def repl(m: re.Match) -> str:
+        cfg = _split_top(m.group(2))
+        grid, block = cfg[0], cfg[1]
+        return (f"::simt::launch(dim3({grid}), dim3({block}), [&]() {{ "
+                f"{m.group(1)}({m.group(3)}); }});")
+
+    out, n = _LAUNCH.subn(repl, src)
+    if n == 0 or "<<<" in out:
+        raise RuntimeError("launch translation failed")
+    out = out.replace('#include "server.h"', "// server left out of the host build")
+    # every array of the device arena gets an allocation of its own (rounded
+    # up to the 16-byte load width), so the sanitizer bounds each array, not
+    # only the arena
+    arena = "T *p = reinterpret_cast<T *>(base + used);"
+    if SEPARATE_ARRAYS:
+        if arena not in out:
+            raise RuntimeError("arena allocation not found")
+        out = out.replace(arena, "T *p = base ? static_cast<T *>(::simt_array_alloc(count * sizeof(T)))"
+                                 " : reinterpret_cast<T *>(base + used);")
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    with open(os.path.join(CSRC, "api.hip")) as fh:
+        src = translate(fh.read())
+    cpp = os.path.join(OUT_DIR, "api_simt.cpp")
+    with open(cpp, "w") as fh:
+        fh.write(src)
+    tmp = LIB + ".tmp"
+    cmd = [CLANG, "-std=c++17", "-O1", "-g", "-fPIC", "-shared",
+           "-fsanitize=address", "-fno-omit-frame-pointer",
+           "-Wno-unknown-pragmas", "-Wno-unused-command-line-argument",
+           "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, "-x", "c++", cpp, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("host build of the kernels failed")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

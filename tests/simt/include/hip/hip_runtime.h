@@ -1,0 +1,546 @@
+// CPU stand-in for <hip/hip_runtime.h>, used only by the test build that
+// runs the library's kernels on the host (tests/simt/build.py).
+//
+// Device code compiles as ordinary C++: kernels become functions, LDS
+// variables become function statics, and every thread of a workgroup runs as
+// a fiber (own stack, switched by a small register-save routine).  A fiber yields at a workgroup barrier and at each
+// cross-lane operation (shuffles, ballots, 16x16x4 matrix products); the
+// scheduler resumes it when the operation can complete:
+//   * a barrier completes when every live thread of the workgroup waits on it;
+//   * a cross-lane operation of a wave completes when every live lane of that
+//     wave is waiting (on a cross-lane operation or on the barrier); lanes
+//     waiting on the barrier are the inactive lanes of a divergent branch and
+//     contribute the value they deposited last.
+// Workgroups of a launch run one after another, the last one first, so the
+// highest per-workgroup workspace slot is the one a work queue hands
+// everything to.  Device memory is host memory from malloc, so a host
+// address sanitizer sees every device access.
+#pragma once
+
+#include <execinfo.h>
+#include <signal.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#if defined(__has_feature)
+#if __has_feature(address_sanitizer)
+#define SIMT_ASAN 1
+#endif
+#endif
+#ifdef SIMT_ASAN
+#include <sanitizer/common_interface_defs.h>
+#endif
+
+// ---- qualifiers ------------------------------------------------------------
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define HIP_SYMBOL(x) (&(x))
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+struct alignas(16) int4 { int x, y, z, w; };
+struct alignas(16) float4 { float x, y, z, w; };
+struct alignas(8) float2 { float x, y; };
+struct alignas(16) double2 { double x, y; };
+
+using std::fmax;
+using std::fmin;
+using std::isfinite;
+using std::isinf;
+using std::isnan;
+using std::sqrt;
+inline int min(int a, int b) { return a < b ? a : b; }
+inline int max(int a, int b) { return a > b ? a : b; }
+inline long long min(long long a, long long b) { return a < b ? a : b; }
+inline long long max(long long a, long long b) { return a > b ? a : b; }
+
+// Fiber switch (x86-64 System V): push the callee-saved registers, store the
+// stack pointer to *from, load `to`, pop them and return into the target.
+extern "C" void simt_switch(void **from, void *to);
+asm(R"(
+  .text
+  .p2align 4
+  .globl simt_switch
+  .hidden simt_switch
+  .type simt_switch,@function
+simt_switch:
+  pushq %rbp
+  pushq %rbx
+  pushq %r12
+  pushq %r13
+  pushq %r14
+  pushq %r15
+  movq %rsp, (%rdi)
+  movq %rsi, %rsp
+  popq %r15
+  popq %r14
+  popq %r13
+  popq %r12
+  popq %rbx
+  popq %rbp
+  ret
+  .size simt_switch, .-simt_switch
+)");
+
+namespace simt {
+
+constexpr int kWaveLanes = 64;
+
+enum State { RUN = 0, BARRIER = 1, WAVE = 2, DONE = 3 };
+enum Kind { SHFL_XOR = 1, SHFL = 2, BALLOT = 3, MFMA64 = 4, MFMA32 = 5 };
+
+struct Lane {
+  int kind = 0, arg = 0, width = 0;
+  const char *file = nullptr;   // call site of the pending cross-lane operation
+  int line = 0;
+  bool go = false;
+  double v = 0.0, a = 0.0, b = 0.0, acc[4] = {0, 0, 0, 0};
+  double r = 0.0, racc[4] = {0, 0, 0, 0};
+  unsigned long long ur = 0;
+  bool pred = false;
+};
+
+struct Fiber {
+  void *sp = nullptr;      // saved stack pointer while switched out
+  char *stack = nullptr;   // from the scheduler's pool
+  State state = RUN;
+  Lane lane;
+};
+
+struct Sched {
+  std::vector<Fiber> f;
+  std::vector<char *> stacks;   // kept across workgroups and launches
+  void *main_sp = nullptr;
+  const std::function<void()> *body = nullptr;
+  int cur = -1, nt = 0, bid = 0, gdim = 1;
+  unsigned long long clock = 0;
+#ifdef SIMT_ASAN
+  void *fake_main = nullptr;
+  const void *main_bottom = nullptr;
+  size_t main_size = 0;
+#endif
+};
+
+inline Sched &S() {
+  static Sched s;
+  return s;
+}
+
+// threadIdx & co. read these (the scheduler keeps them current)
+inline unsigned g_tid = 0, g_bid = 0, g_bdim = 1, g_gdim = 1;
+struct DimRef {
+  const unsigned &x;
+  unsigned y, z;
+};
+
+// switch from the current fiber back to the scheduler
+inline void yield_to_main() {
+  Sched &s = S();
+  Fiber &me = s.f[s.cur];
+#ifdef SIMT_ASAN
+  void *fake = nullptr;
+  __sanitizer_start_switch_fiber(me.state == DONE ? nullptr : &fake, s.main_bottom, s.main_size);
+#endif
+  simt_switch(&me.sp, s.main_sp);
+#ifdef SIMT_ASAN
+  __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#endif
+}
+
+inline void fiber_entry() {
+  Sched &s = S();
+#ifdef SIMT_ASAN
+  __sanitizer_finish_switch_fiber(nullptr, &s.main_bottom, &s.main_size);
+#endif
+  (*s.body)();
+  s.f[s.cur].state = DONE;
+  yield_to_main();
+}
+
+inline void wait(State st) {
+  Sched &s = S();
+  s.f[s.cur].state = st;
+  yield_to_main();
+}
+
+// Complete the cross-lane operations of wave w that can complete: those
+// whose aligned lane segment (the shuffle width; the whole wave for ballots
+// and matrix products) has every live lane waiting at the same call site.
+// Lanes of a segment that are elsewhere are still on their way there (a
+// loop with more trips for them), as on hardware, where the wave runs the
+// longer path first and meets again afterwards.  Returns whether any
+// operation completed.
+inline bool resolve_wave(int w) {
+  Sched &s = S();
+  const int base = w * kWaveLanes, end = std::min(s.nt, base + kWaveLanes);
+  bool any = false;
+  for (int t = base; t < end; ++t) s.f[t].lane.go = false;
+  for (int t = base; t < end; ++t) {
+    const Fiber &x = s.f[t];
+    if (x.state != WAVE || x.lane.go) continue;
+    const Lane &L = x.lane;
+    const int width = (L.kind == SHFL_XOR || L.kind == SHFL) ? L.width : kWaveLanes;
+    const int s0 = base + ((t - base) & ~(width - 1)), s1 = std::min(end, s0 + width);
+    bool ok = true;
+    for (int u = s0; u < s1 && ok; ++u) {
+      const Fiber &y = s.f[u];
+      if (y.state == DONE) continue;
+      ok = y.state == WAVE && y.lane.kind == L.kind && y.lane.line == L.line &&
+           y.lane.file == L.file && y.lane.width == L.width;
+    }
+    if (!ok) continue;
+    for (int u = s0; u < s1; ++u)
+      if (s.f[u].state == WAVE) s.f[u].lane.go = true;
+    any = true;
+  }
+  if (!any) return false;
+  unsigned long long bal = 0;
+  for (int t = base; t < end; ++t)
+    if (s.f[t].lane.go && s.f[t].lane.kind == BALLOT && s.f[t].lane.pred)
+      bal |= 1ull << (t - base);
+  for (int t = base; t < end; ++t) {
+    Fiber &x = s.f[t];
+    if (x.state != WAVE || !x.lane.go) continue;
+    Lane &L = x.lane;
+    const int l = t - base;
+    switch (L.kind) {
+      case SHFL_XOR: {
+        const int src = (l & ~(L.width - 1)) | ((l ^ L.arg) & (L.width - 1));
+        L.r = base + src < end ? s.f[base + src].lane.v : 0.0;
+        break;
+      }
+      case SHFL: {
+        const int src = (l & ~(L.width - 1)) + (L.arg & (L.width - 1));
+        L.r = base + src < end ? s.f[base + src].lane.v : 0.0;
+        break;
+      }
+      case BALLOT:
+        L.ur = bal;
+        break;
+      case MFMA64:
+      case MFMA32: {
+        // A[i][k] from lane 16k + i, B[k][j] from lane 16k + j; output
+        // register v of lane l: row (l/16 + 4v) in FP64, (4(l/16) + v) in
+        // FP32; column l % 16
+        const int c = l & 15, g = l >> 4;
+        for (int v = 0; v < 4; ++v) {
+          const int row = L.kind == MFMA64 ? g + 4 * v : 4 * g + v;
+          double acc = L.acc[v];
+          for (int k = 0; k < 4; ++k) {
+            const int la = base + 16 * k + row, lb = base + 16 * k + c;
+            const double a = la < end ? s.f[la].lane.a : 0.0;
+            const double b = lb < end ? s.f[lb].lane.b : 0.0;
+            acc += a * b;
+          }
+          L.racc[v] = L.kind == MFMA32 ? double(float(acc)) : acc;
+        }
+        break;
+      }
+      default:
+        std::fprintf(stderr, "simt: unknown cross-lane operation\n");
+        std::abort();
+    }
+    x.state = RUN;
+  }
+  return true;
+}
+
+// Run one workgroup of nt threads to completion.
+inline void run_block(int nt, int bid, int gdim, const std::function<void()> &body) {
+  Sched &s = S();
+  constexpr size_t kStack = 1u << 20;
+  s.f.clear();
+  s.f.resize(nt);
+  s.nt = nt;
+  s.bid = bid;
+  s.gdim = gdim;
+  g_bid = (unsigned)bid;
+  g_bdim = (unsigned)nt;
+  g_gdim = (unsigned)gdim;
+  s.body = &body;
+  while ((int)s.stacks.size() < nt) s.stacks.push_back(new char[kStack]);
+  for (int t = 0; t < nt; ++t) {
+    Fiber &x = s.f[t];
+    x.stack = s.stacks[t];
+    // initial frame: six zero registers, then the entry point as the return
+    // address, then a dummy return slot (16-byte alignment at entry)
+    uintptr_t *sp = reinterpret_cast<uintptr_t *>(
+        (reinterpret_cast<uintptr_t>(x.stack) + kStack) & ~uintptr_t(15));
+    *--sp = 0;
+    *--sp = reinterpret_cast<uintptr_t>(&fiber_entry);
+    for (int r = 0; r < 6; ++r) *--sp = 0;
+    x.sp = sp;
+  }
+  const int nw = (nt + kWaveLanes - 1) / kWaveLanes;
+  for (;;) {
+    bool ran = false;
+    for (int t = 0; t < nt; ++t) {
+      if (s.f[t].state != RUN) continue;
+      ran = true;
+      s.cur = t;
+      g_tid = (unsigned)t;
+#ifdef SIMT_ASAN
+      void *fake = nullptr;
+      __sanitizer_start_switch_fiber(&fake, s.f[t].stack, kStack);
+#endif
+      simt_switch(&s.main_sp, s.f[t].sp);
+#ifdef SIMT_ASAN
+      __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#endif
+    }
+    if (ran) continue;
+    // nothing runnable: complete cross-lane operations first, then barriers
+    bool progress = false;
+    for (int w = 0; w < nw; ++w) progress |= resolve_wave(w);
+    if (progress) continue;
+    bool all_done = true, all_barrier = true;
+    for (int t = 0; t < nt; ++t) {
+      all_done &= s.f[t].state == DONE;
+      all_barrier &= s.f[t].state == BARRIER || s.f[t].state == DONE;
+    }
+    if (all_done) break;
+    if (all_barrier) {
+      bool some_live = false;
+      for (int t = 0; t < nt; ++t) some_live |= s.f[t].state == BARRIER;
+      if (some_live) {
+        // a barrier reached by only part of the workgroup (others finished)
+        // is a divergent barrier: report it
+        for (int t = 0; t < nt; ++t)
+          if (s.f[t].state == DONE) {
+            std::fprintf(stderr, "simt: barrier with finished threads (block %d)\n", bid);
+            std::abort();
+          }
+        for (int t = 0; t < nt; ++t) s.f[t].state = RUN;
+        continue;
+      }
+    }
+    std::fprintf(stderr, "simt: deadlock in block %d\n", bid);
+    std::abort();
+  }
+  s.cur = -1;
+}
+
+// SIMT_WATCHDOG=<seconds>: a launch running longer prints where the
+// current thread is and aborts (a thread spinning without yielding keeps
+// the others from running)
+inline void watchdog_handler(int) {
+  char msg[96];
+  const int k = std::snprintf(msg, sizeof msg, "simt: watchdog in block %u thread %u\n", g_bid, g_tid);
+  (void)!write(2, msg, k);
+  void *frames[48];
+  const int nf = backtrace(frames, 48);
+  backtrace_symbols_fd(frames, nf, 2);
+  _exit(3);
+}
+inline void arm_watchdog() {
+  static const int secs = [] {
+    const char *e = std::getenv("SIMT_WATCHDOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (secs <= 0) return;
+  signal(SIGALRM, watchdog_handler);
+  alarm((unsigned)secs);
+}
+
+template <class F>
+inline void launch(dim3 grid, dim3 block, F &&kernel_call) {
+  arm_watchdog();
+  const std::function<void()> body = [&]() { kernel_call(); };
+  for (int b = (int)grid.x - 1; b >= 0; --b) run_block((int)block.x, b, (int)grid.x, body);
+  if (std::getenv("SIMT_WATCHDOG")) alarm(0);
+}
+
+inline Lane &me() { return S().f[S().cur].lane; }
+
+}  // namespace simt
+
+inline const ::simt::DimRef threadIdx{::simt::g_tid, 0u, 0u};
+inline const ::simt::DimRef blockIdx{::simt::g_bid, 0u, 0u};
+inline const ::simt::DimRef blockDim{::simt::g_bdim, 1u, 1u};
+inline const ::simt::DimRef gridDim{::simt::g_gdim, 1u, 1u};
+
+inline void __syncthreads() { ::simt::wait(::simt::BARRIER); }
+inline void __threadfence() {}
+
+template <class T>
+inline T __shfl_xor(T v, int mask, int width = 64, const char *file = __builtin_FILE(),
+                    int line = __builtin_LINE()) {
+  ::simt::Lane &L = ::simt::me();
+  L.kind = ::simt::SHFL_XOR; L.arg = mask; L.width = width; L.v = double(v);
+  L.file = file; L.line = line;
+  ::simt::wait(::simt::WAVE);
+  return T(L.r);
+}
+template <class T>
+inline T __shfl(T v, int src, int width = 64, const char *file = __builtin_FILE(),
+                int line = __builtin_LINE()) {
+  ::simt::Lane &L = ::simt::me();
+  L.kind = ::simt::SHFL; L.arg = src; L.width = width; L.v = double(v);
+  L.file = file; L.line = line;
+  ::simt::wait(::simt::WAVE);
+  return T(L.r);
+}
+inline unsigned long long __ballot(int pred, const char *file = __builtin_FILE(),
+                                   int line = __builtin_LINE()) {
+  ::simt::Lane &L = ::simt::me();
+  L.kind = ::simt::BALLOT; L.pred = pred != 0; L.width = 64;
+  L.file = file; L.line = line;
+  ::simt::wait(::simt::WAVE);
+  return L.ur;
+}
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+
+template <class V>
+inline V simt_mfma(double a, double b, V c, int kind, const char *file = __builtin_FILE(),
+                   int line = __builtin_LINE()) {
+  ::simt::Lane &L = ::simt::me();
+  L.kind = kind; L.a = a; L.b = b; L.width = 64;
+  L.file = file; L.line = line;
+  for (int v = 0; v < 4; ++v) L.acc[v] = double(c[v]);
+  ::simt::wait(::simt::WAVE);
+  V r;
+  for (int v = 0; v < 4; ++v) r[v] = (decltype(c[0] + 0))L.racc[v];
+  return r;
+}
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) \
+  simt_mfma((double)(a), (double)(b), (c), ::simt::MFMA64)
+#define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) \
+  simt_mfma((double)(a), (double)(b), (c), ::simt::MFMA32)
+#define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_s_sleep(x) ((void)0)
+
+inline unsigned long long wall_clock64() { return ++::simt::S().clock; }
+
+// atomics: fibers of one workgroup run on one host thread, one at a time
+template <class T>
+inline T atomicAdd(T *p, T v) { T o = *p; *p = o + v; return o; }
+template <class T>
+inline T atomicOr(T *p, T v) { T o = *p; *p = o | v; return o; }
+template <class T>
+inline T simt_atomic_load(T *p) { return *p; }
+template <class T, class V>
+inline void simt_atomic_store(T *p, V v) { *p = T(v); }
+template <class T, class V>
+inline T simt_atomic_fetch_add(T *p, V v) { T o = *p; *p = T(o + v); return o; }
+#define __hip_atomic_load(p, order, scope) simt_atomic_load(p)
+#define __hip_atomic_store(p, v, order, scope) simt_atomic_store(p, v)
+#define __hip_atomic_fetch_add(p, v, order, scope) simt_atomic_fetch_add(p, v)
+
+// ---- runtime API -------------------------------------------------------------
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorNotSupported = 801, hipErrorInvalidValue = 1 };
+typedef struct simt_stream *hipStream_t;
+typedef struct simt_event { double t; } *hipEvent_t;
+typedef struct simt_graph *hipGraph_t;
+typedef struct simt_graph_exec *hipGraphExec_t;
+typedef struct simt_graph_node *hipGraphNode_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
+enum { hipStreamNonBlocking = 1 };
+enum hipDeviceAttribute_t { hipDeviceAttributeWallClockRate = 1 };
+
+struct hipDeviceProp_t {
+  int multiProcessorCount;
+  size_t sharedMemPerBlock;
+  size_t maxSharedMemoryPerMultiProcessor;
+};
+struct hipFuncAttributes { size_t sharedSizeBytes; };
+struct hipKernelNodeParams {
+  void *func; dim3 gridDim; dim3 blockDim; void **kernelParams; void **extra;
+  unsigned sharedMemBytes;
+};
+
+// workgroups the emulated device runs side by side (the grid size of a
+// work-queue launch)
+#ifndef SIMT_CU_COUNT
+#define SIMT_CU_COUNT 3
+#endif
+
+inline hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
+inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) {
+  p->multiProcessorCount = SIMT_CU_COUNT;
+  p->sharedMemPerBlock = 160 * 1024;
+  p->maxSharedMemoryPerMultiProcessor = 160 * 1024;
+  return hipSuccess;
+}
+inline hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) { *v = 100000; return hipSuccess; }
+inline hipError_t hipFuncGetAttributes(hipFuncAttributes *a, const void *) {
+  a->sharedSizeBytes = 0;
+  return hipSuccess;
+}
+template <class F>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, F, int, size_t) {
+  *n = 1;
+  return hipSuccess;
+}
+inline hipError_t hipMalloc(void **p, size_t bytes) {
+  *p = std::malloc(bytes ? bytes : 1);
+  if (*p) std::memset(*p, 0xA5, bytes);   // device memory starts with junk
+  return *p ? hipSuccess : hipErrorInvalidValue;
+}
+template <class T>
+inline hipError_t hipMalloc(T **p, size_t bytes) { return hipMalloc((void **)p, bytes); }
+// one array of the device arena (kept until the process ends)
+inline void *simt_array_alloc(size_t bytes) {
+  const size_t b = (bytes + 15) & ~size_t(15);
+  void *p = std::malloc(b ? b : 16);
+  if (p) std::memset(p, 0xA5, b ? b : 16);
+  return p;
+}
+inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
+inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) {
+  if (n) std::memmove(d, s, n);
+  return hipSuccess;
+}
+inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
+  return hipMemcpy(d, s, n, k);
+}
+inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+  *s = reinterpret_cast<hipStream_t>(new char(0));
+  return hipSuccess;
+}
+inline hipError_t hipStreamDestroy(hipStream_t s) { delete reinterpret_cast<char *>(s); return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline double simt_now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new simt_event{0.0}; return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t = nullptr) { e->t = simt_now_ms(); return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
+  *ms = float(b->t - a->t);
+  return hipSuccess;
+}
+inline hipError_t hipGetLastError() { return hipSuccess; }
+// cooperative launches and graphs are not emulated
+inline hipError_t hipLaunchCooperativeKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) {
+  return hipErrorNotSupported;
+}
+inline hipError_t hipGraphCreate(hipGraph_t *, unsigned) { return hipErrorNotSupported; }
+inline hipError_t hipGraphAddKernelNode(hipGraphNode_t *, hipGraph_t, const hipGraphNode_t *, size_t,
+                                        const hipKernelNodeParams *) {
+  return hipErrorNotSupported;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t *, hipGraph_t, hipGraphNode_t *, char *, size_t) {
+  return hipErrorNotSupported;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }

@@ -1,0 +1,226 @@
+"""Runs QPs through the host build of the library (its kernels executed on
+the CPU by the SIMT stand-in, every device access address-sanitized) and
+compares each result with the oracle.  Started by the CPU test in a process
+of its own, with the sanitizer runtime preloaded:
+
+    python tests/simt/runner.py [CASE ...]
+
+Prints one line per check ("ok ..." or "FAIL ...") and exits non-zero if a
+check fails; a sanitizer report aborts the process."""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+import time
+import traceback
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import scipy.sparse as sp  # noqa: E402
+
+import oracle  # noqa: E402
+import paper_1711_08013_amd as pm  # noqa: E402
+import qpgen  # noqa: E402
+from qpgen import QP  # noqa: E402
+from tests import gpu_common as gc  # noqa: E402
+
+
+def load():
+    """Bind the package's binding to the host build (the server is not part
+    of it)."""
+    L = ctypes.CDLL(os.path.join(HERE, "_build", "libosqp_simt.so"))
+    L.osqp_error_string.restype = ctypes.c_char_p
+    for name in pm.EXPORTS:
+        if name.startswith("osqp_server"):
+            continue
+        f = getattr(L, name)
+        if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup"):
+            f.restype = ctypes.c_int32
+    L.osqp_cleanup.restype = None
+    L.osqp_batch_cleanup.restype = None
+    pm._lib = L
+    return L
+
+
+def _same_as_oracle(qp, res, exact_iters, objective=True, **kw):
+    """Status, eps test and objective as the GPU parity tests require (the
+    Jacobi path, whose inner solves are inexact, to the eps test only); on
+    the exact-factor paths in FP64 also the oracle's iteration count."""
+    x, y, info = res
+    ref = oracle.solve(qp, **kw)
+    ek = {k: kw[k] for k in ("eps_abs", "eps_rel") if k in kw}
+    row = gc.compare(qp, x, y, info, ref, **ek)
+    if objective and "obj_err" in row:
+        assert row["obj_err"] <= gc.OBJ_TOL, (qp.name, row["obj_err"])
+    if exact_iters:
+        assert info["iter"] == ref.iter, (qp.name, info["iter"], ref.iter)
+    return info
+
+
+def case_paths():
+    """Dense factor, low-rank (Woodbury) and Jacobi-PCG paths, both precisions."""
+    qps = {"dense": qpgen.random_qp(20, qpgen.rng_for(9, 1)),
+           "lowrank": qpgen.config_instance(4, 0, n_range=(100, 101)),
+           "pcg": qpgen.random_qp(20, qpgen.rng_for(9, 2))}
+    code = {"pcg": 1, "dense": 2, "lowrank": 3}
+    for path, qp in qps.items():
+        for prec in ("fp64", "fp32"):
+            res = pm.solve(qp, precision=prec, linsys=path)
+            assert res[2]["linsys"] == code[path], (path, res[2]["linsys"])
+            _same_as_oracle(qp, res, exact_iters=(prec == "fp64" and path != "pcg"),
+                            objective=path != "pcg")
+            yield f"{path} {prec} iter {res[2]['iter']}"
+
+
+def case_mpc():
+    qp = qpgen.mpc(qpgen.rng_for(3, 5), T=5)
+    res = pm.solve(qp, precision="fp64")
+    _same_as_oracle(qp, res, exact_iters=True)
+    yield f"mpc T=5 fp64 iter {res[2]['iter']}"
+
+
+def case_polish():
+    """FP64 polishing, dense and low-rank condensed forms."""
+    for qp in (qpgen.random_qp(15, qpgen.rng_for(9, 3)),
+               qpgen.config_instance(4, 1, n_range=(100, 101))):
+        for prec in ("fp64", "fp32"):
+            res = pm.solve(qp, precision=prec, polish=1)
+            ref = oracle.solve(qp, polish=1)
+            row = gc.compare(qp, *res, ref)
+            if res[2]["polish_status"] == 1 and ref.polish_status == 1:
+                assert row["obj_err"] <= 1e-6, (qp.name, row["obj_err"])
+            yield f"polish {qp.name} {prec} status {res[2]['polish_status']}"
+
+
+def case_tuner():
+    """The launch-shape tuner on a small mixed batch: every shape it times
+    (workgroups of 256 and 512 threads, lane divisors 8..64) runs the
+    kernels, then the tuned batch still matches the oracle and repeats
+    bitwise."""
+    qps = ([qpgen.random_qp(6, qpgen.rng_for(9, 10 + i)) for i in range(2)] +
+           [qpgen.config_instance(4, 2, n_range=(100, 101))])
+    for prec in ("fp32",):
+        b = pm.Batch(qps, precision=prec)
+        t = b.autotune(reps=1)
+        assert t["block_size"] in (256, 512) and 2 <= t["trials"] <= 8, t
+        b.solve()
+        r1 = [b.get(i) for i in range(len(qps))]
+        b.reset()
+        b.solve()
+        r2 = [b.get(i) for i in range(len(qps))]
+        b.close()
+        for (xa, ya, _), (xb, yb, _) in zip(r1, r2):
+            assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+        for qp, r in zip(qps, r1):
+            _same_as_oracle(qp, r, exact_iters=False)
+        yield f"tuner {prec} {t['trials']} shapes, kept {t['block_size']}:{t['lane_div']}"
+
+
+def case_edges():
+    """Scalar QP, no constraints, A = I, LP, empty and free rows."""
+    e = dict(eps_abs=1e-6, eps_rel=1e-6, max_iter=50000)
+    scalar = QP(sp.csr_matrix([[2.0]]), np.array([-4.0]), sp.csr_matrix([[1.0]]),
+                np.array([-1.0]), np.array([1.0]), name="scalar")
+    rng = np.random.default_rng(11)
+    M = rng.standard_normal((6, 6))
+    m0 = QP(sp.csr_matrix(np.triu(M @ M.T + np.eye(6))), rng.standard_normal(6),
+            sp.csr_matrix((0, 6)), np.zeros(0), np.zeros(0), name="m=0")
+    box = qpgen.box_qp(rng.uniform(0.1, 2.0, 9), rng.standard_normal(9), -np.ones(9), np.ones(9))
+    q = rng.standard_normal(8)
+    lp = QP(sp.csr_matrix((8, 8)), q, sp.identity(8, format="csr"), -np.ones(8), np.ones(8),
+            name="box LP")
+    base = qpgen.random_qp(10, qpgen.rng_for(9, 4))
+    A = sp.vstack([base.A, sp.csr_matrix((2, base.n)),
+                   sp.csr_matrix(rng.standard_normal((2, base.n)))], format="csr")
+    rows = QP(base.P, base.q, A, np.concatenate([base.l, [-1.0, 0.0], [-np.inf] * 2]),
+              np.concatenate([base.u, [1.0, 0.0], [np.inf] * 2]), name="empty+free rows")
+    for qp in (scalar, m0, box, lp, rows):
+        res = pm.solve(qp, precision="fp64", **e)
+        if qp.m == 0:
+            assert res[2]["status_name"] == "solved"
+            xs = -np.linalg.solve(qp.full_P().toarray(), qp.q)
+            assert np.allclose(res[0], xs, atol=1e-5)
+        else:
+            _same_as_oracle(qp, res, exact_iters=False, **e)
+        yield f"edge {qp.name}"
+    # all of them in one batch with a regular QP: bitwise as alone
+    qps = [scalar, m0, box, lp, rows, base]
+    b = pm.Batch(qps, precision="fp32")
+    b.solve()
+    mixed = [b.get(i) for i in range(len(qps))]
+    b.close()
+    for qp, (x, y, _) in zip(qps, mixed):
+        xa, ya, _ = pm.solve(qp, precision="fp32")
+        assert np.array_equal(x, xa) and np.array_equal(y, ya), qp.name
+    yield "edge batch bitwise as alone"
+
+
+def case_certificates():
+    A = sp.csr_matrix(np.array([[1.0, 0.0], [1.0, 0.0], [0.0, 1.0]]))
+    pinf = QP(sp.csr_matrix(np.eye(2)), np.zeros(2), A, np.array([1.0, -np.inf, -1.0]),
+              np.array([np.inf, 0.0, 1.0]), name="primal infeasible")
+    dinf = qpgen.box_qp(np.zeros(5), -np.ones(5), np.zeros(5), np.inf * np.ones(5))
+    for prec in ("fp64", "fp32"):
+        assert pm.solve(pinf, precision=prec)[2]["status_name"] == "primal_infeasible"
+        assert pm.solve(dinf, precision=prec)[2]["status_name"] == "dual_infeasible"
+        yield f"certificates {prec}"
+
+
+def case_appendix():
+    """Equality QP, Huber fitting and SVM at small sizes."""
+    for qp in (qpgen.eq_qp(12, qpgen.rng_for(9, 5)),
+               qpgen.huber(qpgen.rng_for(7, 1), 2, m_data=24),
+               qpgen.svm(qpgen.rng_for(7, 2), 2, m_data=24)):
+        for prec in ("fp64", "fp32"):
+            res = pm.solve(qp, precision=prec)
+            _same_as_oracle(qp, res, exact_iters=False)
+            yield f"{qp.name} {prec} linsys {res[2]['linsys']}"
+
+
+def case_updates():
+    """Vector and matrix updates with warm start (Section 6)."""
+    qp = qpgen.random_qp(12, qpgen.rng_for(9, 6))
+    s = pm.Solver(qp, precision="fp64")
+    s.solve()
+    q2 = qp.q + 0.1
+    s.update_vectors(q=q2)
+    s.solve()
+    qpv = QP(qp.P, q2, qp.A, qp.l, qp.u, name="q updated")
+    _same_as_oracle(qpv, s.result(), exact_iters=False)
+    A2 = qp.A.copy()
+    A2.data = A2.data * 1.1
+    s.update_matrices(A=A2)
+    s.solve()
+    x, y, info = s.result()
+    qpm = QP(qp.P, q2, A2, qp.l, qp.u, name="A updated")
+    row = gc.compare(qpm, x, y, info, oracle.solve(qpm))
+    assert row.get("obj_err", 0.0) <= gc.OBJ_TOL
+    s.close()
+    yield "updates"
+
+
+CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "tuner": case_tuner,
+         "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,
+         "updates": case_updates}
+
+
+def main(names):
+    load()
+    failed = 0
+    for name in names or list(CASES):
+        t0 = time.time()
+        try:
+            for msg in CASES[name]():
+                print(f"ok {name}: {msg} ({time.time() - t0:.1f} s)", flush=True)
+        except Exception:
+            failed += 1
+            print(f"FAIL {name}:\n{traceback.format_exc()}", flush=True)
+    return 1 if failed else 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -1,0 +1,65 @@
+"""The library's kernels run on the CPU: the library source is built for the
+host against a stand-in HIP runtime that executes every workgroup thread as
+a fiber with wave-level shuffles, ballots and 16x16x4 matrix products
+emulated (tests/simt), under the host address sanitizer.  The same C ABI
+then solves the cases of tests/simt/runner.py -- every linear-system path
+in both precisions, polishing, the launch-shape tuner across all its
+shapes, degenerate inputs, certificates, the appendix problem classes and
+the parametric updates -- and each result is compared with the oracle.  A
+device-memory access outside its allocation aborts the run with the
+sanitizer's report.  This checks the kernels' logic and indexing, not the
+GPU's timing or its hardware-specific behaviour."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIMT = os.path.join(ROOT, "tests", "simt")
+sys.path.insert(0, SIMT)
+
+import build as simt_build  # noqa: E402
+
+# the runner's cases, split over two processes that run side by side
+GROUPS = [["tuner"], ["paths", "mpc", "polish", "edges", "certificates", "appendix", "updates"]]
+EXPECTED_OK = {"tuner": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6, "certificates": 2,
+               "appendix": 6, "updates": 1}
+
+
+@pytest.fixture(scope="module")
+def simt_lib():
+    if not os.path.exists(simt_build.CLANG):
+        pytest.skip("host clang++ not available")
+    try:
+        asan = simt_build.asan_runtime()
+    except (RuntimeError, subprocess.CalledProcessError, FileNotFoundError):
+        pytest.skip("address-sanitizer runtime not available")
+    simt_build.build()
+    return asan
+
+
+def test_kernels_on_cpu_match_oracle(simt_lib):
+    env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
+               SIMT_WATCHDOG="300")
+    procs = [subprocess.Popen([sys.executable, os.path.join(SIMT, "runner.py"), *g],
+                              stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                              env=env, cwd=ROOT) for g in GROUPS]
+    outs = []
+    for p in procs:
+        try:
+            out, _ = p.communicate(timeout=900)
+        except subprocess.TimeoutExpired:
+            p.kill()
+            out, _ = p.communicate()
+        outs.append((p.returncode, out))
+    text = "\n".join(o for _, o in outs)
+    print(text)
+    for rc, out in outs:
+        assert rc == 0, out[-4000:]
+    assert "ERROR: AddressSanitizer" not in text
+    for name, k in EXPECTED_OK.items():
+        got = sum(1 for line in text.splitlines() if line.startswith(f"ok {name}:"))
+        assert got == k, (name, got, k)
