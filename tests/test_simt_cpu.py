@@ -19,9 +19,17 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SIMT = os.path.join(ROOT, "tests", "simt")
-sys.path.insert(0, SIMT)
 
-import build as simt_build  # noqa: E402
+
+def _load_builder():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("simt_build", os.path.join(SIMT, "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+simt_build = _load_builder()
 
 # the runner's cases, split over two processes that run side by side
 GROUPS = [["tuner"], ["paths", "mpc", "polish", "edges", "certificates", "appendix", "updates"]]
