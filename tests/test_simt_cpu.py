@@ -71,3 +71,17 @@ def test_kernels_on_cpu_match_oracle(simt_lib):
     for name, k in EXPECTED_OK.items():
         got = sum(1 for line in text.splitlines() if line.startswith(f"ok {name}:"))
         assert got == k, (name, got, k)
+
+
+def test_gpu_edge_case_file_on_cpu_kernels(simt_lib):
+    """The GPU edge-case tests (degenerate inputs against closed forms, the
+    oracle and the solve alone) with the emulated kernels in place of the
+    device."""
+    env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
+               SIMT_WATCHDOG="300")
+    r = subprocess.run([sys.executable, os.path.join(SIMT, "pytest_on_simt.py"),
+                        os.path.join(ROOT, "tests", "test_gpu_y_edge_cases.py"), "-m", "gpu", "-q"],
+                       capture_output=True, text=True, env=env, cwd=ROOT, timeout=900)
+    print(r.stdout[-3000:])
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    assert "11 passed" in r.stdout
