@@ -11,7 +11,9 @@
 //     wave is waiting (on a cross-lane operation or on the barrier); lanes
 //     waiting on the barrier are the inactive lanes of a divergent branch and
 //     contribute the value they deposited last.
-// Workgroups of a launch run one after another, the last one first, so the
+// Threads run in alternating ascending and descending order between
+// synchronisation points.  Workgroups of a launch run one after another,
+// the last one first, so the
 // highest per-workgroup workspace slot is the one a work queue hands
 // everything to.  Device memory is host memory from malloc, so a host
 // address sanitizer sees every device access.
@@ -288,9 +290,15 @@ inline void run_block(int nt, int bid, int gdim, const std::function<void()> &bo
     x.sp = sp;
   }
   const int nw = (nt + kWaveLanes - 1) / kWaveLanes;
+  // sweeps alternate between ascending and descending thread order, so a
+  // read that is not ordered after its write by a barrier sees the stale
+  // value in one of the two orders
+  bool down = false;
   for (;;) {
     bool ran = false;
-    for (int t = 0; t < nt; ++t) {
+    down = !down;
+    for (int k = 0; k < nt; ++k) {
+      const int t = down ? nt - 1 - k : k;
       if (s.f[t].state != RUN) continue;
       ran = true;
       s.cur = t;
