@@ -77,8 +77,29 @@ def translate(src: str) -> str:
     return out
 
 
-def build(verbose: bool = False) -> str:
+def _sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    files = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))]
+    files += [os.path.join(ROOT, "include", "osqp_mi.h"), os.path.abspath(__file__),
+              os.path.join(HERE, "include", "hip", "hip_runtime.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    h.update(CLANG.encode() + str(SEPARATE_ARRAYS).encode())
+    return h.hexdigest()
+
+
+def build(verbose: bool = False, force: bool = False) -> str:
+    """Builds the host library unless one built from the same sources is
+    there."""
     os.makedirs(OUT_DIR, exist_ok=True)
+    stamp = os.path.join(OUT_DIR, "sources.sha256")
+    digest = _sources_hash()
+    if not force and os.path.exists(LIB) and os.path.exists(stamp):
+        with open(stamp) as fh:
+            if fh.read().strip() == digest:
+                return LIB
     with open(os.path.join(CSRC, "api.hip")) as fh:
         src = translate(fh.read())
     cpp = os.path.join(OUT_DIR, "api_simt.cpp")
@@ -97,8 +118,10 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("host build of the kernels failed")
     os.replace(tmp, LIB)
+    with open(stamp, "w") as fh:
+        fh.write(digest + "\n")
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, force="--force" in sys.argv))
