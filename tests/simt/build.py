@@ -74,7 +74,45 @@ def translate(src: str) -> str:
             raise RuntimeError("arena allocation not found")
         out = out.replace(arena, "T *p = base ? static_cast<T *>(::simt_array_alloc(count * sizeof(T)))"
                                  " : reinterpret_cast<T *>(base + used);")
-    return out
+    return out + GRAPH_BINDERS
+
+
+# binders of the kernels the library puts into graphs (argument types as in
+# their definitions)
+GRAPH_BINDERS = r"""
+namespace {
+template <class T>
+bool simt_bind_kernels() {
+  using namespace osqpmi;
+  ::simt::register_kernel((const void *)solve_wg_kernel<T>, [](void **a) {
+    Batch<T> b = *static_cast<Batch<T> *>(a[0]);
+    const int *list = *static_cast<const int **>(a[1]);
+    const int nl = *static_cast<int *>(a[2]), slot = *static_cast<int *>(a[3]);
+    return std::function<void()>([=]() { solve_wg_kernel<T>(b, list, nl, slot); });
+  });
+  ::simt::register_kernel((const void *)polish_wg_kernel<T>, [](void **a) {
+    Batch<T> b = *static_cast<Batch<T> *>(a[0]);
+    const int *list = *static_cast<const int **>(a[1]);
+    const int nl = *static_cast<int *>(a[2]), slot = *static_cast<int *>(a[3]);
+    double *ws = *static_cast<double **>(a[4]);
+    const long long stride = *static_cast<long long *>(a[5]);
+    const int rmax = *static_cast<int *>(a[6]);
+    return std::function<void()>([=]() { polish_wg_kernel<T>(b, list, nl, slot, ws, stride, rmax); });
+  });
+  return true;
+}
+const bool simt_bound = [] {
+  using namespace osqpmi;
+  ::simt::register_kernel((const void *)reset_counters_kernel, [](void **a) {
+    int *c = *static_cast<int **>(a[0]);
+    const int n = *static_cast<int *>(a[1]);
+    GridBarrier *bar = *static_cast<GridBarrier **>(a[2]);
+    return std::function<void()>([=]() { reset_counters_kernel(c, n, bar); });
+  });
+  return simt_bind_kernels<float>() && simt_bind_kernels<double>();
+}();
+}  // namespace
+"""
 
 
 def _sources_hash() -> str:

@@ -151,6 +151,40 @@ def case_tuner_mixed():
     yield f"tuner on the mixed batch: {t['trials']} shapes, kept {t['block_size']}:{t['lane_div']}"
 
 
+def case_graph():
+    """Replays of the solve graph against the eager solve, bitwise, with
+    eager work between the replays; after a new launch shape the graph is
+    rebuilt and again matches."""
+    qps = ([qpgen.random_qp(10, qpgen.rng_for(9, 20 + i)) for i in range(2)] +
+           [qpgen.config_instance(4, 3, n_range=(100, 101)), qpgen.mpc(qpgen.rng_for(3, 6), T=5)])
+
+    def same(ra, rb):
+        for (xa, ya, ia), (xb, yb, ib) in zip(ra, rb):
+            assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+            assert ia["iter"] == ib["iter"] and ia["polish_status"] == ib["polish_status"]
+
+    b = pm.Batch(qps, precision="fp32", polish=1)
+    b.solve()
+    eager = [b.get(i) for i in range(len(qps))]
+    for _ in range(2):
+        b.reset()
+        b.solve_subset([1, 3])
+        b.reset()
+        b.solve_graph()
+        same(eager, [b.get(i) for i in range(len(qps))])
+    b.set_shape(512, 16)
+    b.reset()
+    b.solve()
+    eager2 = [b.get(i) for i in range(len(qps))]
+    b.reset()
+    b.solve_graph()
+    same(eager2, [b.get(i) for i in range(len(qps))])
+    b.close()
+    for qp, r in zip(qps, eager):
+        _same_as_oracle(qp, r, exact_iters=False, polish=1)
+    yield "graph replays bitwise as eager, rebuilt after a shape change"
+
+
 def case_edges():
     """Scalar QP, no constraints, A = I, LP, empty and free rows."""
     e = dict(eps_abs=1e-6, eps_rel=1e-6, max_iter=50000)
@@ -235,7 +269,7 @@ def case_updates():
 
 
 CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "tuner": case_tuner,
-         "tuner_mixed": case_tuner_mixed,
+         "tuner_mixed": case_tuner_mixed, "graph": case_graph,
          "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,
          "updates": case_updates}
 

@@ -4,8 +4,9 @@ a fiber with wave-level shuffles, ballots and 16x16x4 matrix products
 emulated (tests/simt), under the host address sanitizer.  The same C ABI
 then solves the cases of tests/simt/runner.py -- every linear-system path
 in both precisions, polishing, the launch-shape tuner across all its
-shapes, degenerate inputs, certificates, the appendix problem classes and
-the parametric updates -- and each result is compared with the oracle.  A
+shapes, graph replays, degenerate inputs, certificates, the appendix
+problem classes and the parametric updates -- and each result is compared
+with the oracle.  A
 device-memory access outside its allocation aborts the run with the
 sanitizer's report.  This checks the kernels' logic and indexing, not the
 GPU's timing or its hardware-specific behaviour."""
@@ -31,10 +32,11 @@ def _load_builder():
 
 simt_build = _load_builder()
 
-# the runner's cases, split over two processes that run side by side
-GROUPS = [["tuner"], ["paths", "mpc", "polish", "edges", "certificates", "appendix", "updates"]]
-EXPECTED_OK = {"tuner": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6, "certificates": 2,
-               "appendix": 6, "updates": 1}
+# the runner's cases, split over three processes that run side by side
+GROUPS = [["tuner"], ["graph", "paths", "mpc"],
+          ["polish", "edges", "certificates", "appendix", "updates"]]
+EXPECTED_OK = {"tuner": 1, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
+               "certificates": 2, "appendix": 6, "updates": 1}
 
 
 @pytest.fixture(scope="module")
