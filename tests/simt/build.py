@@ -77,8 +77,8 @@ def translate(src: str) -> str:
     return out + GRAPH_BINDERS
 
 
-# binders of the kernels the library puts into graphs (argument types as in
-# their definitions)
+# binders of the kernels the library puts into graphs or launches
+# cooperatively (argument types as in their definitions)
 GRAPH_BINDERS = r"""
 namespace {
 template <class T>
@@ -98,6 +98,22 @@ bool simt_bind_kernels() {
     const long long stride = *static_cast<long long *>(a[5]);
     const int rmax = *static_cast<int *>(a[6]);
     return std::function<void()>([=]() { polish_wg_kernel<T>(b, list, nl, slot, ws, stride, rmax); });
+  });
+  ::simt::register_kernel((const void *)solve_grid_kernel<T>, [](void **a) {
+    Batch<T> b = *static_cast<Batch<T> *>(a[0]);
+    const int *list = *static_cast<const int **>(a[1]);
+    const int nl = *static_cast<int *>(a[2]);
+    double *partials = *static_cast<double **>(a[3]);
+    GridBarrier *bar = *static_cast<GridBarrier **>(a[4]);
+    return std::function<void()>([=]() { solve_grid_kernel<T>(b, list, nl, partials, bar); });
+  });
+  ::simt::register_kernel((const void *)scale_grid_kernel<T>, [](void **a) {
+    Batch<T> b = *static_cast<Batch<T> *>(a[0]);
+    const int *list = *static_cast<const int **>(a[1]);
+    const int nl = *static_cast<int *>(a[2]);
+    double *partials = *static_cast<double **>(a[3]);
+    GridBarrier *bar = *static_cast<GridBarrier **>(a[4]);
+    return std::function<void()>([=]() { scale_grid_kernel<T>(b, list, nl, partials, bar); });
   });
   return true;
 }

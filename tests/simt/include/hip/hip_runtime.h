@@ -48,7 +48,10 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
-#define __shared__ static
+// LDS variables live in a section of their own, so that a cooperative
+// launch (several workgroups side by side) can give each workgroup its own
+// copy: the section is swapped when the scheduler moves to another workgroup
+#define __shared__ static __attribute__((section("simt_lds")))
 #define HIP_SYMBOL(x) (&(x))
 
 struct dim3 {
@@ -99,6 +102,9 @@ simt_switch:
   ret
   .size simt_switch, .-simt_switch
 )");
+
+extern "C" char __start_simt_lds[] __attribute__((weak));
+extern "C" char __stop_simt_lds[] __attribute__((weak));
 
 namespace simt {
 
@@ -188,9 +194,8 @@ inline void wait(State st) {
 // loop with more trips for them), as on hardware, where the wave runs the
 // longer path first and meets again afterwards.  Returns whether any
 // operation completed.
-inline bool resolve_wave(int w) {
+inline bool resolve_wave(int base, int end) {
   Sched &s = S();
-  const int base = w * kWaveLanes, end = std::min(s.nt, base + kWaveLanes);
   bool any = false;
   for (int t = base; t < end; ++t) s.f[t].lane.go = false;
   for (int t = base; t < end; ++t) {
@@ -263,21 +268,22 @@ inline bool resolve_wave(int w) {
   return true;
 }
 
-// Run one workgroup of nt threads to completion.
-inline void run_block(int nt, int bid, int gdim, const std::function<void()> &body) {
+// Run nblk workgroups of nt threads side by side (blocks bid0, bid0+1, ...)
+// to completion: one for an ordinary launch, the whole grid for a
+// cooperative one, whose grid barrier spins with s_sleep (a yield here).
+inline void run_blocks(int nblk, int nt, int bid0, int gdim, const std::function<void()> &body) {
   Sched &s = S();
   constexpr size_t kStack = 1u << 20;
+  const int total = nblk * nt;
   s.f.clear();
-  s.f.resize(nt);
+  s.f.resize(total);
   s.nt = nt;
-  s.bid = bid;
   s.gdim = gdim;
-  g_bid = (unsigned)bid;
   g_bdim = (unsigned)nt;
   g_gdim = (unsigned)gdim;
   s.body = &body;
-  while ((int)s.stacks.size() < nt) s.stacks.push_back(new char[kStack]);
-  for (int t = 0; t < nt; ++t) {
+  while ((int)s.stacks.size() < total) s.stacks.push_back(new char[kStack]);
+  for (int t = 0; t < total; ++t) {
     Fiber &x = s.f[t];
     x.stack = s.stacks[t];
     // initial frame: six zero registers, then the entry point as the return
@@ -289,7 +295,12 @@ inline void run_block(int nt, int bid, int gdim, const std::function<void()> &bo
     for (int r = 0; r < 6; ++r) *--sp = 0;
     x.sp = sp;
   }
-  const int nw = (nt + kWaveLanes - 1) / kWaveLanes;
+  // per-workgroup LDS images when several workgroups run side by side
+  const size_t lds_bytes = (__start_simt_lds && __stop_simt_lds)
+                               ? size_t(__stop_simt_lds - __start_simt_lds) : 0;
+  std::vector<std::vector<char>> lds;
+  int lds_loaded = 0;
+  if (nblk > 1 && lds_bytes) lds.assign(nblk, std::vector<char>(__start_simt_lds, __stop_simt_lds));
   // sweeps alternate between ascending and descending thread order, so a
   // read that is not ordered after its write by a barrier sees the stale
   // value in one of the two orders
@@ -297,12 +308,19 @@ inline void run_block(int nt, int bid, int gdim, const std::function<void()> &bo
   for (;;) {
     bool ran = false;
     down = !down;
-    for (int k = 0; k < nt; ++k) {
-      const int t = down ? nt - 1 - k : k;
+    for (int k = 0; k < total; ++k) {
+      const int t = down ? total - 1 - k : k;
       if (s.f[t].state != RUN) continue;
       ran = true;
+      if (!lds.empty() && t / nt != lds_loaded) {
+        std::memcpy(lds[lds_loaded].data(), __start_simt_lds, lds_bytes);
+        lds_loaded = t / nt;
+        std::memcpy(__start_simt_lds, lds[lds_loaded].data(), lds_bytes);
+      }
       s.cur = t;
-      g_tid = (unsigned)t;
+      s.bid = bid0 + t / nt;
+      g_tid = (unsigned)(t % nt);
+      g_bid = (unsigned)s.bid;
 #ifdef SIMT_ASAN
       void *fake = nullptr;
       __sanitizer_start_switch_fiber(&fake, s.f[t].stack, kStack);
@@ -312,36 +330,45 @@ inline void run_block(int nt, int bid, int gdim, const std::function<void()> &bo
       __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
 #endif
     }
-    if (ran) continue;
-    // nothing runnable: complete cross-lane operations first, then barriers
-    bool progress = false;
-    for (int w = 0; w < nw; ++w) progress |= resolve_wave(w);
-    if (progress) continue;
-    bool all_done = true, all_barrier = true;
-    for (int t = 0; t < nt; ++t) {
-      all_done &= s.f[t].state == DONE;
-      all_barrier &= s.f[t].state == BARRIER || s.f[t].state == DONE;
-    }
-    if (all_done) break;
-    if (all_barrier) {
-      bool some_live = false;
-      for (int t = 0; t < nt; ++t) some_live |= s.f[t].state == BARRIER;
-      if (some_live) {
+    // cross-lane operations, then workgroup barriers, that can complete
+    bool progress = false, all_done = true;
+    for (int b = 0; b < nblk; ++b) {
+      const int b0 = b * nt, b1 = b0 + nt;
+      for (int w0 = b0; w0 < b1; w0 += kWaveLanes)
+        progress |= resolve_wave(w0, std::min(b1, w0 + kWaveLanes));
+      bool all_barrier = true, some_barrier = false, some_done = false;
+      for (int t = b0; t < b1; ++t) {
+        const State st = s.f[t].state;
+        all_barrier &= st == BARRIER || st == DONE;
+        some_barrier |= st == BARRIER;
+        some_done |= st == DONE;
+        all_done &= st == DONE;
+      }
+      if (all_barrier && some_barrier) {
         // a barrier reached by only part of the workgroup (others finished)
         // is a divergent barrier: report it
-        for (int t = 0; t < nt; ++t)
-          if (s.f[t].state == DONE) {
-            std::fprintf(stderr, "simt: barrier with finished threads (block %d)\n", bid);
-            std::abort();
-          }
-        for (int t = 0; t < nt; ++t) s.f[t].state = RUN;
-        continue;
+        if (some_done) {
+          std::fprintf(stderr, "simt: barrier with finished threads (block %d)\n", bid0 + b);
+          std::abort();
+        }
+        for (int t = b0; t < b1; ++t) s.f[t].state = RUN;
+        progress = true;
       }
     }
-    std::fprintf(stderr, "simt: deadlock in block %d\n", bid);
-    std::abort();
+    if (all_done) break;
+    if (!ran && !progress) {
+      std::fprintf(stderr, "simt: deadlock (blocks %d..%d)\n", bid0, bid0 + nblk - 1);
+      std::abort();
+    }
   }
   s.cur = -1;
+}
+
+// yield from a spin-wait (other threads, also of other workgroups, run)
+inline void spin_yield() {
+  Sched &s = S();
+  s.f[s.cur].state = RUN;
+  yield_to_main();
 }
 
 // SIMT_WATCHDOG=<seconds>: a launch running longer prints where the
@@ -370,7 +397,15 @@ template <class F>
 inline void launch(dim3 grid, dim3 block, F &&kernel_call) {
   arm_watchdog();
   const std::function<void()> body = [&]() { kernel_call(); };
-  for (int b = (int)grid.x - 1; b >= 0; --b) run_block((int)block.x, b, (int)grid.x, body);
+  for (int b = (int)grid.x - 1; b >= 0; --b) run_blocks(1, (int)block.x, b, (int)grid.x, body);
+  if (std::getenv("SIMT_WATCHDOG")) alarm(0);
+}
+
+template <class F>
+inline void launch_cooperative(dim3 grid, dim3 block, F &&kernel_call) {
+  arm_watchdog();
+  const std::function<void()> body = [&]() { kernel_call(); };
+  run_blocks((int)grid.x, (int)block.x, 0, (int)grid.x, body);
   if (std::getenv("SIMT_WATCHDOG")) alarm(0);
 }
 
@@ -431,7 +466,7 @@ inline V simt_mfma(double a, double b, V c, int kind, const char *file = __built
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) \
   simt_mfma((double)(a), (double)(b), (c), ::simt::MFMA32)
 #define __builtin_amdgcn_readfirstlane(x) (x)
-#define __builtin_amdgcn_s_sleep(x) ((void)0)
+#define __builtin_amdgcn_s_sleep(x) ::simt::spin_yield()
 
 inline unsigned long long wall_clock64() { return ++::simt::S().clock; }
 
@@ -537,11 +572,7 @@ inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
   return hipSuccess;
 }
 inline hipError_t hipGetLastError() { return hipSuccess; }
-// cooperative launches and graphs are not emulated
-inline hipError_t hipLaunchCooperativeKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) {
-  return hipErrorNotSupported;
-}
-// Graphs of kernel nodes, replayed in the order the nodes were added (each
+// Graphs of kernel nodes (and cooperative launches), replayed in the order the nodes were added (each
 // node depends on the one before it where the library builds them).  A
 // kernel reaches a node through a binder registered for its address, which
 // copies the argument values when the node is added, as the runtime does.
@@ -563,6 +594,17 @@ struct GraphNode {
 struct simt_graph { std::vector<::simt::GraphNode> nodes; };
 struct simt_graph_exec { std::vector<::simt::GraphNode> nodes; };
 struct simt_graph_node { int index; };
+// cooperative launch: the whole grid side by side
+inline hipError_t hipLaunchCooperativeKernel(const void *fn, dim3 grid, dim3 block, void **args,
+                                             size_t, hipStream_t) {
+  for (auto &kb : ::simt::kernel_binders())
+    if (kb.first == fn) {
+      const std::function<void()> call = kb.second(args);
+      ::simt::launch_cooperative(grid, block, call);
+      return hipSuccess;
+    }
+  return hipErrorNotSupported;
+}
 inline hipError_t hipGraphCreate(hipGraph_t *g, unsigned) { *g = new simt_graph; return hipSuccess; }
 inline hipError_t hipGraphAddKernelNode(hipGraphNode_t *node, hipGraph_t g, const hipGraphNode_t *,
                                         size_t, const hipKernelNodeParams *p) {
