@@ -185,6 +185,30 @@ def case_graph():
     yield "graph replays bitwise as eager, rebuilt after a shape change"
 
 
+def case_grid():
+    """A QP large enough for the whole-grid team (cooperative launch, grid
+    barriers, two-level reductions), 50 ADMM iterations in both precisions:
+    the same status as the oracle and an objective near its iterate's (the
+    Jacobi inner solves are inexact); the solve graph is refused."""
+    qp = qpgen.config_instance(1, 0, n=400, m=4000)
+    for prec in ("fp64", "fp32"):
+        b = pm.Batch([qp], precision=prec, linsys="pcg", max_iter=50)
+        try:
+            b.solve_graph()
+            raise AssertionError("graph accepted for a whole-grid QP")
+        except pm.OSQPError as e:
+            assert e.code == 13, e.code
+        b.solve()
+        x, y, info = b.get(0)
+        b.close()
+        ref = oracle.solve(qp, max_iter=50)
+        assert info["status_name"] == ref.status == "max_iter_reached", (info["status_name"], ref.status)
+        assert np.isfinite(x).all() and np.isfinite(y).all()
+        err = abs(info["obj_val"] - ref.obj_val) / max(1.0, abs(ref.obj_val))
+        assert err <= 1e-2, err
+        yield f"grid team {prec}: obj {info['obj_val']:.6f} (oracle {ref.obj_val:.6f})"
+
+
 def case_edges():
     """Scalar QP, no constraints, A = I, LP, empty and free rows."""
     e = dict(eps_abs=1e-6, eps_rel=1e-6, max_iter=50000)
@@ -269,7 +293,7 @@ def case_updates():
 
 
 CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "tuner": case_tuner,
-         "tuner_mixed": case_tuner_mixed, "graph": case_graph,
+         "tuner_mixed": case_tuner_mixed, "graph": case_graph, "grid": case_grid,
          "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,
          "updates": case_updates}
 

@@ -4,7 +4,8 @@ a fiber with wave-level shuffles, ballots and 16x16x4 matrix products
 emulated (tests/simt), under the host address sanitizer.  The same C ABI
 then solves the cases of tests/simt/runner.py -- every linear-system path
 in both precisions, polishing, the launch-shape tuner across all its
-shapes, graph replays, degenerate inputs, certificates, the appendix
+shapes, graph replays, the whole-grid team of a cooperative launch,
+degenerate inputs, certificates, the appendix
 problem classes and the parametric updates -- and each result is compared
 with the oracle.  A
 device-memory access outside its allocation aborts the run with the
@@ -32,10 +33,10 @@ def _load_builder():
 
 simt_build = _load_builder()
 
-# the runner's cases, split over three processes that run side by side
-GROUPS = [["tuner"], ["graph", "paths", "mpc"],
+# the runner's cases, split over four processes that run side by side
+GROUPS = [["tuner"], ["grid"], ["graph", "paths", "mpc"],
           ["polish", "edges", "certificates", "appendix", "updates"]]
-EXPECTED_OK = {"tuner": 1, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
+EXPECTED_OK = {"tuner": 1, "grid": 2, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
                "certificates": 2, "appendix": 6, "updates": 1}
 
 
