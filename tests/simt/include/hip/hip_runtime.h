@@ -2,21 +2,24 @@
 // runs the library's kernels on the host (tests/simt/build.py).
 //
 // Device code compiles as ordinary C++: kernels become functions, LDS
-// variables become function statics, and every thread of a workgroup runs as
-// a fiber (own stack, switched by a small register-save routine).  A fiber yields at a workgroup barrier and at each
-// cross-lane operation (shuffles, ballots, 16x16x4 matrix products); the
-// scheduler resumes it when the operation can complete:
-//   * a barrier completes when every live thread of the workgroup waits on it;
-//   * a cross-lane operation of a wave completes when every live lane of that
-//     wave is waiting (on a cross-lane operation or on the barrier); lanes
-//     waiting on the barrier are the inactive lanes of a divergent branch and
-//     contribute the value they deposited last.
+// variables become function statics in a section of their own, and every
+// thread of a workgroup runs as a fiber (own stack, switched by a small
+// register-save routine).  A fiber yields at a workgroup barrier, at each
+// cross-lane operation (shuffles, ballots, 16x16x4 matrix products) and in
+// a spin-wait; the scheduler resumes it when the operation can complete:
+//   * a barrier completes when every live thread of the workgroup waits on it
+//     (one that only part of the workgroup reaches is reported);
+//   * a cross-lane operation completes when every live lane of its aligned
+//     segment (the shuffle width, else the wave) waits at the same call
+//     site; lanes elsewhere are still on a longer path to it, which is the
+//     order in which a wave runs a divergent branch.
 // Threads run in alternating ascending and descending order between
-// synchronisation points.  Workgroups of a launch run one after another,
-// the last one first, so the
-// highest per-workgroup workspace slot is the one a work queue hands
-// everything to.  Device memory is host memory from malloc, so a host
-// address sanitizer sees every device access.
+// synchronisation points.  The workgroups of an ordinary launch run one
+// after another, the last one first (so the highest per-workgroup workspace
+// slot is the one a work queue hands everything to); those of a cooperative
+// launch run side by side, each with its own copy of the LDS section.
+// Device memory is host memory from malloc, so a host address sanitizer
+// sees every device access.
 #pragma once
 
 #include <execinfo.h>
