@@ -94,25 +94,30 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_1711_08013_amd/build.py")
-        L = ctypes.CDLL(LIB_PATH)
-        for name in EXPORTS:
-            getattr(L, name)
-        L.osqp_error_string.restype = ctypes.c_char_p
-        for name in EXPORTS:
-            if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup",
-                            "osqp_server_destroy"):
-                getattr(L, name).restype = ctypes.c_int32
-        L.osqp_cleanup.restype = None
-        L.osqp_batch_cleanup.restype = None
-        L.osqp_server_destroy.restype = None
-        L.osqp_server_create.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
-                                         ctypes.c_void_p]
-        L.osqp_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
-                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-        L.osqp_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-        _lib = L
+        _lib = _configure(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def _configure(L: ctypes.CDLL) -> ctypes.CDLL:
+    """Checks that every exported function is there and sets the result and
+    argument types the C ABI declares."""
+    for name in EXPORTS:
+        getattr(L, name)
+    L.osqp_error_string.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup",
+                        "osqp_server_destroy"):
+            getattr(L, name).restype = ctypes.c_int32
+    L.osqp_cleanup.restype = None
+    L.osqp_batch_cleanup.restype = None
+    L.osqp_server_destroy.restype = None
+    L.osqp_server_create.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                     ctypes.c_void_p]
+    L.osqp_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.osqp_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    return L
 
 
 def device_count() -> int:

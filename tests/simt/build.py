@@ -5,8 +5,8 @@ paper_1711_08013_amd/build.py).
 The library source is compiled as plain C++ against the stand-in runtime in
 tests/simt/include/hip/hip_runtime.h.  Two mechanical edits are made to a
 copy of it: each triple-chevron launch becomes a call of simt::launch with
-the kernel call in a lambda, and the server (which launches from its own
-thread) is left out.  The build uses the host address sanitizer, so every
+the kernel call in a lambda, and every array of the device arena gets an
+allocation of its own.  The build uses the host address sanitizer, so every
 device-memory access of the kernels is bounds-checked against the
 allocation it belongs to."""
 from __future__ import annotations
@@ -23,6 +23,9 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libosqp_simt.so")
 CLANG = os.environ.get("SIMT_CXX", "/opt/rocm/llvm/bin/clang++")
 SEPARATE_ARRAYS = os.environ.get("SIMT_ONE_ARENA", "") == ""
+# the server launches from its scheduler thread, one launch at a time, which
+# the stand-in runtime (one scheduler, launches run when issued) allows
+WITH_SERVER = os.environ.get("SIMT_NO_SERVER", "") == ""
 
 
 def asan_runtime() -> str:
@@ -64,7 +67,8 @@ def translate(src: str) -> str:
     out, n = _LAUNCH.subn(repl, src)
     if n == 0 or "<<<" in out:
         raise RuntimeError("launch translation failed")
-    out = out.replace('#include "server.h"', "// server left out of the host build")
+    if not WITH_SERVER:
+        out = out.replace('#include "server.h"', "// server left out of the host build")
     # every array of the device arena gets an allocation of its own (rounded
     # up to the 16-byte load width), so the sanitizer bounds each array, not
     # only the arena
@@ -140,7 +144,7 @@ def _sources_hash() -> str:
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode() + fh.read())
-    h.update(CLANG.encode() + str(SEPARATE_ARRAYS).encode())
+    h.update(CLANG.encode() + str(SEPARATE_ARRAYS).encode() + str(WITH_SERVER).encode())
     return h.hexdigest()
 
 

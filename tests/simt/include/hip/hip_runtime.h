@@ -563,6 +563,8 @@ inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
 }
 inline hipError_t hipStreamDestroy(hipStream_t s) { delete reinterpret_cast<char *>(s); return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+// launches run to completion when they are issued
+inline hipError_t hipStreamQuery(hipStream_t) { return hipSuccess; }
 inline double simt_now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();

@@ -30,20 +30,9 @@ from tests import gpu_common as gc  # noqa: E402
 
 
 def load():
-    """Bind the package's binding to the host build (the server is not part
-    of it)."""
-    L = ctypes.CDLL(os.path.join(HERE, "_build", "libosqp_simt.so"))
-    L.osqp_error_string.restype = ctypes.c_char_p
-    for name in pm.EXPORTS:
-        if name.startswith("osqp_server"):
-            continue
-        f = getattr(L, name)
-        if name not in ("osqp_error_string", "osqp_cleanup", "osqp_batch_cleanup"):
-            f.restype = ctypes.c_int32
-    L.osqp_cleanup.restype = None
-    L.osqp_batch_cleanup.restype = None
-    pm._lib = L
-    return L
+    """Bind the package's binding to the host build."""
+    pm._lib = pm._configure(ctypes.CDLL(os.path.join(HERE, "_build", "libosqp_simt.so")))
+    return pm._lib
 
 
 def _same_as_oracle(qp, res, exact_iters, objective=True, **kw):
