@@ -198,6 +198,31 @@ def case_grid():
         yield f"grid team {prec}: obj {info['obj_val']:.6f} (oracle {ref.obj_val:.6f})"
 
 
+def case_server():
+    """The continuous-batching server: fresh QPs, and a repeated structure
+    (same key, new expected returns) re-solved warm in its resident pool."""
+    rng = qpgen.rng_for(4, 901)
+    F, Dd, mu = qpgen.portfolio_model(rng, 100)
+    reqs = [(qpgen.random_qp(8, qpgen.rng_for(9, 30 + i)), 0) for i in range(3)]
+    for _ in range(3):
+        mu = 0.8 * mu + 0.2 * rng.standard_normal(mu.size)
+        reqs.append((qpgen.portfolio(rng, model=(F, Dd, mu)), 7))
+    with pm.Server(hbm_budget_bytes=1 << 30, max_slots=16) as sv:
+        tickets = [sv.submit(qp, key=k) for qp, k in reqs]
+        outs = [sv.wait(t) for t in tickets]
+        stats = sv.stats()
+    assert stats["completed"] == len(reqs), stats
+    # fresh requests: the oracle's objective; warm re-solves of the pool stop
+    # at another eps-solution (the oracle warm-started from the same point
+    # stops there too), so they are held to the status and the eps test
+    seen = set()
+    for (qp, key), (x, y, info, lat) in zip(reqs, outs):
+        fresh = key == 0 or key not in seen
+        seen.add(key)
+        _same_as_oracle(qp, (x, y, info), exact_iters=False, objective=fresh)
+    yield f"server: {stats['completed']} requests in {stats['batches']} launches"
+
+
 def case_edges():
     """Scalar QP, no constraints, A = I, LP, empty and free rows."""
     e = dict(eps_abs=1e-6, eps_rel=1e-6, max_iter=50000)
@@ -283,6 +308,7 @@ def case_updates():
 
 CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "tuner": case_tuner,
          "tuner_mixed": case_tuner_mixed, "graph": case_graph, "grid": case_grid,
+         "server": case_server,
          "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,
          "updates": case_updates}
 

@@ -4,8 +4,8 @@ a fiber with wave-level shuffles, ballots and 16x16x4 matrix products
 emulated (tests/simt), under the host address sanitizer.  The same C ABI
 then solves the cases of tests/simt/runner.py -- every linear-system path
 in both precisions, polishing, the launch-shape tuner across all its
-shapes, graph replays, the whole-grid team of a cooperative launch,
-degenerate inputs, certificates, the appendix
+shapes, graph replays, the whole-grid team of a cooperative launch, the
+serving loop, degenerate inputs, certificates, the appendix
 problem classes and the parametric updates -- and each result is compared
 with the oracle.  A
 device-memory access outside its allocation aborts the run with the
@@ -35,9 +35,9 @@ simt_build = _load_builder()
 
 # the runner's cases, split over four processes that run side by side
 GROUPS = [["tuner"], ["grid"], ["graph", "paths", "mpc"],
-          ["polish", "edges", "certificates", "appendix", "updates"]]
+          ["polish", "edges", "certificates", "appendix", "updates", "server"]]
 EXPECTED_OK = {"tuner": 1, "grid": 2, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
-               "certificates": 2, "appendix": 6, "updates": 1}
+               "certificates": 2, "appendix": 6, "updates": 1, "server": 1}
 
 
 @pytest.fixture(scope="module")
