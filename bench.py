@@ -35,8 +35,9 @@ WORKLOADS = {
                            "k=n/10, F 50% dense", {"polish": 1}),
     "mpc": (3, 4096, "batched linear MPC, 4096 QPs, nx=20, nu=10, T in [5,20]", {}),
 }
-# launch shape (workgroup size : lane divisor) applied before the timed steps
-# unless --autotune is given: the shape the tuner kept for the workload
+# launch shape (workgroup size : lane divisor) applied before the timed
+# steps: the fastest of the shapes timed earlier on each workload (the same
+# workgroup size the setup picks, so the grid stays the setup's)
 DEFAULT_SHAPES = {"portfolio": "512:32", "mpc": "256:32"}
 
 
@@ -290,8 +291,6 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-parametric", action="store_true")
     ap.add_argument("--no-high-accuracy", action="store_true")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the launch shapes before the timed steps and keep the fastest")
     ap.add_argument("--shape", default=None,
                     help="BLOCK:LANE_DIV launch shape for the timed steps (default: the "
                          "workload's entry in DEFAULT_SHAPES; 'setup' keeps the setup's shape)")
@@ -316,12 +315,7 @@ def main():
     print(f"# setup {setup_s:.2f} s", file=sys.stderr, flush=True)
     tuning = None
     shape_arg = args.shape if args.shape else DEFAULT_SHAPES.get(args.workload, "setup")
-    if args.autotune:
-        t0 = time.perf_counter()
-        tuning = batch.autotune(reps=1)
-        tuning["tune_s"] = round(time.perf_counter() - t0, 3)
-        print(f"# autotune {tuning}", file=sys.stderr, flush=True)
-    elif shape_arg != "setup":
+    if shape_arg != "setup":
         blk, div = (int(v) for v in shape_arg.split(":"))
         batch.set_shape(blk, div)
         tuning = {"block_size": blk, "lane_div": div, "applied": True}

@@ -104,8 +104,9 @@ typedef struct {
   osqp_int linsys;         /* OSQP_LINSYS_*, default AUTO                    */
   osqp_int pcg_max_iter;   /* PCG iterations per ADMM step, default 50       */
   osqp_int block_size;     /* threads per workgroup, 0 = chosen by size     */
-                           /* (512 for long passes, else 256; the autotuner */
-                           /* may change it); else fixed, a multiple of 64  */
+                           /* (512 for long passes, else 256;               */
+                           /* osqp_batch_set_shape may change it); else     */
+                           /* fixed, a multiple of 64                       */
   void *stream;            /* hipStream_t to run on, NULL = own stream       */
 } osqp_settings;
 
@@ -126,7 +127,7 @@ typedef struct {
   osqp_float factor_time, pcg_time, update_time, check_time;
 } osqp_info;
 
-/* Outcome of osqp_batch_autotune. */
+/* Outcome of osqp_batch_autotune (which is switched off, see there). */
 typedef struct {
   osqp_int block_size;     /* threads per workgroup chosen                   */
   osqp_int lane_div;       /* lanes per row ~ mean row length / lane_div      */
@@ -224,32 +225,29 @@ osqp_int osqp_batch_solve_subset_async(osqp_batch *b, const osqp_int *idx, osqp_
 osqp_int osqp_batch_sync(osqp_batch *b);
 /* Enqueue the whole-batch solve as one replay of a HIP graph (counter reset,
  * the persistent workgroup solve, polishing), built on the first call for the
- * batch's current launch shape and rebuilt after osqp_batch_autotune.  Same
+ * batch's current launch shape and rebuilt after osqp_batch_set_shape.  Same
  * results as osqp_batch_solve_async; results after osqp_batch_sync.  For
  * callers that replay the solve of resident QPs many times (Section 6:
  * parametric re-solves after update_vectors / warm_start).  Returns
  * OSQP_ERR_UNSUPPORTED when the batch holds QPs solved by the whole grid (their
  * launch is cooperative); osqp_batch_last_kernel_ms then spans the graph. */
 osqp_int osqp_batch_solve_graph_async(osqp_batch *b);
-/* Tune the launch shape of the batch solve on the batch itself: workgroup
- * sizes 256 and 512 threads (only settings.block_size if that is nonzero)
- * times lane divisors 8, 16, 32 and 64 (lanes per CSR row ~ the QP's mean row
- * length / divisor, a power of two up to 64).  Each distinct shape is timed
- * by `reps` (1..16) cold solves of the whole batch, device time from HIP
- * events, minimum taken; the fastest shape stays for every later solve, and
- * the batch is reset (iterates zero, scaling redone).  A larger grid gets
- * its own per-workgroup workspace; shapes whose workspace cannot be
- * allocated are skipped.  Results of later solves stay within the solver's
- * tolerances but are not bit-identical across shapes (reduction order).
- * `out` may be NULL. */
+/* Launch-shape tuner: switched off.  Returns OSQP_ERR_UNSUPPORTED for every
+ * batch (OSQP_ERR_NOT_SETUP for a NULL handle) and leaves `out` untouched.
+ * The device was lost during its GPU test in several runs without a cause
+ * being shown, so no shape is timed on the device; callers apply a known
+ * shape with osqp_batch_set_shape. */
 osqp_int osqp_batch_autotune(osqp_batch *b, osqp_int reps, osqp_tuning *out);
-/* Apply a launch shape directly (for instance one osqp_batch_autotune chose
- * for batches of the same kind earlier): block_size a multiple of 64 in
- * [64, 512] (equal to settings.block_size if that is nonzero), lane_div in
- * [1, 1024].  Waits for the batch's stream; iterates, results and the
- * scaling are kept (osqp_batch_reset redoes the scaling, whose sums then
- * run in the new shape's order);  OSQP_ERR_SETTINGS for a shape out of range, OSQP_ERR_ALLOC when the
- * larger grid's workspace cannot be allocated (the old shape then stays). */
+/* Apply a launch shape: block_size a multiple of 64 in [64, 512] (equal to
+ * settings.block_size if that is nonzero), lane_div in [1, 1024] (lanes per
+ * CSR row ~ the QP's mean row length / lane_div, a power of two up to 64).
+ * The grid follows the occupancy of the new workgroup size but never exceeds
+ * the grid sized at setup (the per-workgroup workspaces keep their size;
+ * nothing is allocated).  Waits for the batch's stream; iterates, results
+ * and the scaling are kept (osqp_batch_reset redoes the scaling, whose sums
+ * then run in the new shape's order, so results across shapes agree to the
+ * solver's tolerance, not bitwise).  OSQP_ERR_SETTINGS for a shape out of
+ * range. */
 osqp_int osqp_batch_set_shape(osqp_batch *b, osqp_int block_size, osqp_int lane_div);
 /* Re-run the device-side Ruiz scaling from the resident unscaled data and
  * reset every iterate to zero (a fresh solve of the same problems). */

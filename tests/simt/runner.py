@@ -85,59 +85,36 @@ def case_polish():
             yield f"polish {qp.name} {prec} status {res[2]['polish_status']}"
 
 
-def case_tuner():
-    """The launch-shape tuner on a small mixed batch: every shape it times
-    (workgroups of 256 and 512 threads, lane divisors 8..64) runs the
-    kernels, then the tuned batch still matches the oracle and repeats
-    bitwise."""
+def case_shapes():
+    """Every launch shape osqp_batch_set_shape accepts for the solve
+    (workgroups of 256 and 512 threads, lane divisors 8..64) on a small
+    mixed batch: each matches the oracle and repeats bitwise; the tuner
+    entry point is switched off (OSQP_ERR_UNSUPPORTED)."""
     qps = ([qpgen.random_qp(6, qpgen.rng_for(9, 10 + i)) for i in range(2)] +
            [qpgen.config_instance(4, 2, n_range=(100, 101))])
-    for prec in ("fp32",):
-        b = pm.Batch(qps, precision=prec)
-        t = b.autotune(reps=1)
-        assert t["block_size"] in (256, 512) and 2 <= t["trials"] <= 8, t
-        b.solve()
-        r1 = [b.get(i) for i in range(len(qps))]
-        b.reset()
-        b.solve()
-        r2 = [b.get(i) for i in range(len(qps))]
-        b.close()
-        for (xa, ya, _), (xb, yb, _) in zip(r1, r2):
-            assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
-        for qp, r in zip(qps, r1):
-            _same_as_oracle(qp, r, exact_iters=False)
-        yield f"tuner {prec} {t['trials']} shapes, kept {t['block_size']}:{t['lane_div']}"
-
-
-def case_tuner_mixed():
-    """(Not in the CPU suite: about four minutes.)  The tuner on four QPs
-    of the GPU tuner test's mixed batch -- a random QP large enough for
-    512-thread workgroups, a random QP of the benchmark's size, an MPC QP
-    and a factor-model portfolio -- in FP32; then the oracle, bitwise
-    repetition, and the kept shape applied to a fresh batch."""
-    qps = ([qpgen.config_instance(1, 0, n=120), qpgen.config_instance(1, 1),
-            qpgen.config_instance(3, 0), qpgen.config_instance(4, 0, n_range=(100, 400))])
     b = pm.Batch(qps, precision="fp32")
-    t = b.autotune(reps=1)
-    b.solve()
-    r1 = [b.get(i) for i in range(len(qps))]
-    b.reset()
-    b.solve()
-    r2 = [b.get(i) for i in range(len(qps))]
+    try:
+        b.autotune(reps=1)
+        raise AssertionError("the tuner entry point should be switched off")
+    except pm.OSQPError as e:
+        assert e.code == 13, e.code
+    shapes = 0
+    for block in (256, 512):
+        for div in (8, 16, 32, 64):
+            b.set_shape(block, div)
+            b.reset()
+            b.solve()
+            r1 = [b.get(i) for i in range(len(qps))]
+            b.reset()
+            b.solve()
+            r2 = [b.get(i) for i in range(len(qps))]
+            for (xa, ya, _), (xb, yb, _) in zip(r1, r2):
+                assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+            for qp, r in zip(qps, r1):
+                _same_as_oracle(qp, r, exact_iters=False)
+            shapes += 1
     b.close()
-    for (xa, ya, _), (xb, yb, _) in zip(r1, r2):
-        assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
-    for qp, r in zip(qps, r1):
-        _same_as_oracle(qp, r, exact_iters=False)
-    b = pm.Batch(qps, precision="fp32")
-    b.set_shape(t["block_size"], t["lane_div"])
-    b.reset()
-    b.solve()
-    r3 = [b.get(i) for i in range(len(qps))]
-    b.close()
-    for (xa, ya, _), (xb, yb, _) in zip(r1, r3):
-        assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
-    yield f"tuner on the mixed batch: {t['trials']} shapes, kept {t['block_size']}:{t['lane_div']}"
+    yield f"set_shape over {shapes} shapes, each matching the oracle"
 
 
 def case_graph():
@@ -306,8 +283,8 @@ def case_updates():
     yield "updates"
 
 
-CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "tuner": case_tuner,
-         "tuner_mixed": case_tuner_mixed, "graph": case_graph, "grid": case_grid,
+CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "shapes": case_shapes,
+         "graph": case_graph, "grid": case_grid,
          "server": case_server,
          "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,
          "updates": case_updates}
@@ -316,7 +293,7 @@ CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "tuner": c
 def main(names):
     load()
     failed = 0
-    for name in names or [c for c in CASES if c != "tuner_mixed"]:
+    for name in names or list(CASES):
         t0 = time.time()
         try:
             for msg in CASES[name]():

@@ -1,5 +1,5 @@
-"""Batched-path launch machinery on the GPU: the launch-shape autotuner and the
-replayable graph of the solve launches, both through the C ABI."""
+"""Batched-path launch machinery on the GPU: launch shapes and the replayable
+graph of the solve launches, through the C ABI."""
 from __future__ import annotations
 
 import numpy as np
@@ -29,16 +29,6 @@ def _mixed_qps():
             [qpgen.config_instance(4, i, n_range=(100, 400)) for i in range(4)])
 
 
-# The GPU device was lost during test_autotune_keeps_parity[fp32], the first
-# GPU test of the suite, in four runs: twice before any kernel had been
-# launched, twice after its tuning solves.  No cause in this library has been
-# shown, so the tuner's tests stay skipped and the benchmark applies a fixed
-# launch shape instead of tuning.
-TUNER_SKIP = pytest.mark.skip(
-    reason="device lost during the tuner test in four runs (cause not shown); "
-           "the launch-shape tuner is kept off the GPU")
-
-
 def _results(b, count):
     return [b.get(i) for i in range(count)]
 
@@ -50,56 +40,34 @@ def _same(ra, rb):
         assert ia["polish_status"] == ib["polish_status"]
 
 
-@TUNER_SKIP
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_autotune_keeps_parity(pm, precision):
-    """After the tuner has timed the launch shapes and kept the fastest, the
-    batch still reaches the oracle's statuses and objectives, and two solves
-    in a row agree bitwise."""
-    qps = _mixed_qps()
-    print(f"autotune {precision}: {len(qps)} QPs", flush=True)
-    b = pm.Batch(qps, precision=precision)
-    t = b.autotune(reps=1)
-    print(f"  tuning {t}", flush=True)
-    assert t["block_size"] in (256, 512)
-    assert t["lane_div"] in (8, 16, 32, 64)
-    assert 2 <= t["trials"] <= 8
-    assert 0.0 < t["best_ms"] <= t["default_ms"]
+def test_autotune_switched_off(pm):
+    """The launch-shape tuner is switched off (the device was lost during
+    its GPU test in several runs, cause not shown): the entry point returns
+    OSQP_ERR_UNSUPPORTED and the batch still solves."""
+    qps = [qpgen.config_instance(3, i) for i in range(2)]
+    b = pm.Batch(qps, precision="fp32")
+    with pytest.raises(pm.OSQPError) as e:
+        b.autotune(reps=1)
+    assert e.value.code == 13
     b.solve()
-    r1 = _results(b, len(qps))
-    b.reset()
-    b.solve()
-    r2 = _results(b, len(qps))
+    res = _results(b, len(qps))
     b.close()
-    _same(r1, r2)
-    # the chosen shape applied directly to a fresh batch gives the same bits
-    # once the scaling is redone under it (its sums follow the shape's order)
-    b = pm.Batch(qps, precision=precision)
-    b.set_shape(t["block_size"], t["lane_div"])
-    b.reset()
-    b.solve()
-    r3 = _results(b, len(qps))
-    b.close()
-    _same(r1, r3)
-    rows = [gc.compare(q, *r, oracle.solve(q)) for q, r in zip(qps, r1)]
-    gc.summarize(rows, f"autotuned {precision}")
-    gc.assert_obj_parity(rows, f"autotuned {precision}")
+    for q, r in zip(qps, res):
+        gc.compare(q, *r, oracle.solve(q))
 
 
-@TUNER_SKIP
-def test_autotune_respects_fixed_block(pm):
-    """A block size fixed in the settings is the only one tried, and a shape
-    with another block size is refused."""
-    qps = [qpgen.config_instance(3, i) for i in range(4)]
+def test_set_shape_refuses_other_block(pm):
+    """A block size fixed in the settings is the only one set_shape accepts."""
+    qps = [qpgen.config_instance(3, i) for i in range(2)]
     b = pm.Batch(qps, precision="fp32", block_size=256)
     with pytest.raises(pm.OSQPError) as e:
         b.set_shape(512, 16)
     assert e.value.code == 6
-    t = b.autotune(reps=1)
+    b.set_shape(256, 32)
+    b.reset()
     b.solve()
     res = _results(b, len(qps))
     b.close()
-    assert t["block_size"] == 256 and 1 <= t["trials"] <= 4
     for q, r in zip(qps, res):
         gc.compare(q, *r, oracle.solve(q))
 
@@ -111,7 +79,7 @@ def test_graph_replays_match_eager(pm, precision):
     new launch shape the graph is rebuilt and again matches."""
     qps = _mixed_qps()
     print(f"graph {precision}: {len(qps)} QPs, polish on", flush=True)
-    b = pm.Batch(qps, precision=precision, polish=1)
+    b = pm.Batch(qps, precision=precision, polish=1, block_size=512)
     b.solve()
     eager = _results(b, len(qps))
     for rep in range(3):
@@ -121,7 +89,9 @@ def test_graph_replays_match_eager(pm, precision):
         b.solve_graph()
         print(f"  replay {rep}", flush=True)
         _same(eager, _results(b, len(qps)))
-    b.set_shape(256, 16)
+    # a new lane divisor at the same workgroup size (the grid stays the one
+    # sized at setup)
+    b.set_shape(512, 32)
     b.reset()
     b.solve()
     eager2 = _results(b, len(qps))

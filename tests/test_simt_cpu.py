@@ -3,7 +3,7 @@ host against a stand-in HIP runtime that executes every workgroup thread as
 a fiber with wave-level shuffles, ballots and 16x16x4 matrix products
 emulated (tests/simt), under the host address sanitizer.  The same C ABI
 then solves the cases of tests/simt/runner.py -- every linear-system path
-in both precisions, polishing, the launch-shape tuner across all its
+in both precisions, polishing, every launch shape set_shape accepts
 shapes, graph replays, the whole-grid team of a cooperative launch, the
 serving loop, degenerate inputs, certificates, the appendix
 problem classes and the parametric updates -- and each result is compared
@@ -34,9 +34,9 @@ def _load_builder():
 simt_build = _load_builder()
 
 # the runner's cases, split over four processes that run side by side
-GROUPS = [["tuner"], ["grid"], ["graph", "paths", "mpc"],
+GROUPS = [["shapes"], ["grid"], ["graph", "paths", "mpc"],
           ["polish", "edges", "certificates", "appendix", "updates", "server"]]
-EXPECTED_OK = {"tuner": 1, "grid": 2, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
+EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
                "certificates": 2, "appendix": 6, "updates": 1, "server": 1}
 
 
