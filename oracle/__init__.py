@@ -6,6 +6,7 @@ module and shares no code with it.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import dataclasses
 import os
@@ -21,14 +22,15 @@ STATUS = {1: "solved", 2: "primal_infeasible", 3: "dual_infeasible",
           4: "max_iter_reached", 5: "time_limit_reached", 6: "unsolved"}
 
 
-def build() -> str:
-    """Compile oracle.c into liboracle.so (plain gcc, -O3, no CPU-specific flags)."""
-    tmp = _SO + ".tmp"
+def build(src: str = _SRC, out: str = _SO) -> str:
+    """Compile oracle.c (or another copy of it, `src`) into a shared library
+    (plain gcc, -O3, no CPU-specific flags)."""
+    tmp = out + ".tmp"
     subprocess.check_call(["gcc", "-O3", "-std=c11", "-D_POSIX_C_SOURCE=200809L",
                            "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
-                           "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _SO)
-    return _SO
+                           "-I", _HERE, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
 
 
 class _Problem(ctypes.Structure):
@@ -58,18 +60,38 @@ class _Info(ctypes.Structure):
 _lib = None
 
 
+def _open(path: str):
+    lib = ctypes.CDLL(path)
+    lib.orc_solve.restype = ctypes.c_int
+    lib.orc_ldl_solve.restype = ctypes.c_int
+    lib.orc_mindeg.restype = ctypes.c_int
+    lib.orc_ruiz.restype = ctypes.c_int
+    lib.orc_rho_update.restype = ctypes.c_double
+    lib.orc_rho_update.argtypes = [ctypes.c_double] * 5
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
             build()
-        lib = ctypes.CDLL(_SO)
-        lib.orc_solve.restype = ctypes.c_int
-        lib.orc_ldl_solve.restype = ctypes.c_int
-        lib.orc_mindeg.restype = ctypes.c_int
-        lib.orc_ruiz.restype = ctypes.c_int
-        _lib = lib
+        _lib = _open(_SO)
     return _lib
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Run the oracle functions of this module on another build of the
+    oracle (a copy with a planted mistake, for the tests that check that the
+    pins catch it); the usual library is restored afterwards."""
+    global _lib
+    saved = _lib
+    _lib = _open(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def default_settings() -> dict:
@@ -154,6 +176,12 @@ def solve(qp, x_ws=None, y_ws=None, **settings) -> Result:
                   eps_prim=info.eps_prim, eps_dual=info.eps_dual, rho_bar=info.rho_bar,
                   setup_time=info.setup_time, solve_time=info.solve_time,
                   polish_time=info.polish_time)
+
+
+def rho_update(rho_bar: float, prim_res: float, prim_norm: float, dual_res: float,
+               dual_norm: float) -> float:
+    """The Section 5.2 rho-bar rule the solver applies at each check."""
+    return float(_load().orc_rho_update(rho_bar, prim_res, prim_norm, dual_res, dual_norm))
 
 
 def ruiz(qp, iters: int = 10):

@@ -816,6 +816,25 @@ static void set_rho(const work_qp *w, const double *l_in, const double *u_in, do
   }
 }
 
+/* Section 5.2 rule for rho-bar: the square root of the ratio of the scaled
+ * primal residual, normalised by max(||Abar xbar||, ||zbar||), to the scaled
+ * dual residual, normalised by max(||Pbar xbar||, ||Abar' ybar||, ||qbar||),
+ * multiplies the current value.  Readings: no update when a normaliser or
+ * the dual residual is zero; the new value is clamped to [1e-6, 1e6]; it is
+ * taken when it is at least 5 times larger or smaller than the current one
+ * (the paper's time-based condition is replaced by evaluating the rule at
+ * every termination check).  Returns the value to use: the new one, or
+ * rho_bar itself when the rule does not apply. */
+double orc_rho_update(double rho_bar, double prim_res, double prim_norm, double dual_res,
+                      double dual_norm) {
+  if (!(prim_norm > 0.0) || !(dual_norm > 0.0) || !(dual_res > 0.0)) return rho_bar;
+  double ratio = (prim_res / prim_norm) / (dual_res / dual_norm);
+  double rnew = rho_bar * sqrt(ratio);
+  rnew = dmin(dmax(rnew, 1e-6), 1e6);
+  if (rnew >= 5.0 * rho_bar || rnew <= rho_bar / 5.0) return rnew;
+  return rho_bar;
+}
+
 int orc_solve(const orc_problem *pb, const orc_settings *s, const double *x_ws,
               const double *y_ws, double *x_out, double *y_out, double *z_out,
               orc_info *info) {
@@ -912,14 +931,11 @@ int orc_solve(const orc_problem *pb, const orc_settings *s, const double *x_ws,
     }
     if (k == s->max_iter) { status = ORC_MAX_ITER_REACHED; break; }
     if (s->adaptive_rho) {
-      /* Section 5.2 rho-bar rule, scaled residuals.  Readings: skip when a
-       * normaliser or the dual residual is zero; clamp to [1e-6, 1e6];
-       * apply when the change is at least 5x, at every check. */
-      if (res.prim_norm_s > 0.0 && res.dual_norm_s > 0.0 && res.dual_res_s > 0.0) {
-        double ratio = (res.prim_res_s / res.prim_norm_s) / (res.dual_res_s / res.dual_norm_s);
-        double rnew = rho_bar * sqrt(ratio);
-        rnew = dmin(dmax(rnew, 1e-6), 1e6);
-        if (rnew > 5.0 * rho_bar || rnew < rho_bar / 5.0) {
+      /* Section 5.2 rho-bar rule on the scaled residuals, at every check */
+      {
+        double rnew = orc_rho_update(rho_bar, res.prim_res_s, res.prim_norm_s, res.dual_res_s,
+                                     res.dual_norm_s);
+        if (rnew != rho_bar) {
           rho_bar = rnew;
           set_rho(&w, pb->l, pb->u, rho_bar, rho, rhoinv);
           for (int i = 0; i < m; ++i) K.Kx[K.diag_pos[n + i]] = -rhoinv[i];

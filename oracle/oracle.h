@@ -55,6 +55,12 @@ int orc_solve(const orc_problem *pb, const orc_settings *s,
               const double *x_ws, const double *y_ws,
               double *x, double *y, double *z, orc_info *info);
 
+/* Section 5.2 rho-bar rule on scaled residuals and their normalisers (the
+ * solver applies it at every termination check): returns the new rho-bar, or
+ * rho_bar unchanged when the rule does not fire. */
+double orc_rho_update(double rho_bar, double prim_res, double prim_norm, double dual_res,
+                      double dual_norm);
+
 /* Modified Ruiz equilibration alone: D (n), E (m), *c. */
 int orc_ruiz(const orc_problem *pb, int iters, double *D, double *E, double *c);
 

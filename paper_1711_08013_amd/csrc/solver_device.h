@@ -1166,11 +1166,12 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     if (k >= set.max_iter) { status = 4; break; }
     if (bad) { status = 6; break; }
     // rho-bar rule (Section 5.2), scaled quantities; readings: skip on zero
-    // normalisers, clamp to [1e-6, 1e6], apply at a 5x change
+    // normalisers, clamp to [1e-6, 1e6], apply when at least 5x larger or
+    // smaller
     if (set.adaptive_rho && pnorm > 0.0 && dnorm > 0.0 && drs > 0.0) {
       double rnew = rho_bar * sqrt((prs / pnorm) / (drs / dnorm));
       rnew = fmin(fmax(rnew, 1e-6), 1e6);
-      if (rnew > 5.0 * rho_bar || rnew < rho_bar / 5.0) {
+      if (rnew >= 5.0 * rho_bar || rnew <= rho_bar / 5.0) {
         rho_bar = rnew;
         ++rho_updates;
         set_rho_and_precond(tm, v, rho_bar, set.sigma);

@@ -356,6 +356,93 @@ def test_ruiz_equilibrates_columns(oracle_lib):
     assert np.allclose(np.abs(Ab).max(axis=1), 1.0, atol=1e-6)
 
 
+def _read_ruiz_golden():
+    """Cases of tests/golden/ruiz_passes.txt: (name, qp, [(passes, D, E, c)])."""
+    from fractions import Fraction
+    cases, cur = [], None
+    num = lambda t: float(Fraction(t))  # noqa: E731
+    with open(os.path.join(GOLDEN, "ruiz_passes.txt")) as fh:
+        for raw in fh:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, _, rest = line.partition(" ")
+            if key == "case":
+                cur = {"name": rest.strip(), "passes": []}
+                cases.append(cur)
+            elif key in ("P", "A"):
+                cur[key] = [[num(t) for t in r.split()] for r in rest.split(";")]
+            elif key == "q":
+                cur["q"] = [num(t) for t in rest.split()]
+            elif key == "pass":
+                parts = rest.split("|")
+                head = parts[0].split()
+                cur["passes"].append((int(head[0]), [num(t) for t in head[1:]],
+                                      [num(t) for t in parts[1].split()], num(parts[2].strip())))
+    out = []
+    for c in cases:
+        m = len(c["A"])
+        qp = _qp_dense(c["P"], c["q"], c["A"], -np.ones(m), np.ones(m), c["name"])
+        out.append((c["name"], qp, c["passes"]))
+    return out
+
+
+@pytest.mark.parametrize("case", _read_ruiz_golden(), ids=lambda c: c[0])
+def test_ruiz_passes_hand_values(oracle_lib, case):
+    """Section 5.1, modified Ruiz equilibration with its cost scaling: D, E
+    and c after one and two passes equal the values worked out by hand in
+    tests/golden/ruiz_passes.txt (P with an off-diagonal entry, q nonzero; one
+    case where the mean column norm of Pbar sets gamma, one where ||qbar||
+    does)."""
+    name, qp, passes = case
+    for k, D_want, E_want, c_want in passes:
+        D, E, c = oracle_lib.ruiz(qp, k)
+        assert np.allclose(D, D_want, rtol=1e-14, atol=0), (name, k, D, D_want)
+        assert np.allclose(E, E_want, rtol=1e-14, atol=0), (name, k, E, E_want)
+        assert c == pytest.approx(c_want, rel=1e-14), (name, k, c, c_want)
+
+
+# ---------------------------------------------------------------- rho-bar rule
+def _read_rho_rule():
+    rows = []
+    with open(os.path.join(GOLDEN, "rho_rule.txt")) as fh:
+        for raw in fh:
+            t = raw.split("#", 1)[0].split()
+            if t:
+                rows.append((t[0], *[float(v) for v in t[1:]]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _read_rho_rule(), ids=lambda r: r[0])
+def test_rho_rule_hand_values(oracle_lib, row):
+    """Section 5.2 rule for rho-bar on synthetic residuals against values
+    worked out by hand (tests/golden/rho_rule.txt): the square root of the
+    ratio, which normaliser goes with which residual, the 5x gate and its
+    boundary, the [1e-6, 1e6] clamp applied before the gate, and the
+    zero-normaliser skip."""
+    name, rho, pr, pn, dr, dn, want = row
+    got = oracle_lib.rho_update(rho, pr, pn, dr, dn)
+    assert got == pytest.approx(want, rel=1e-14, abs=0), (name, got, want)
+
+
+def test_rho_rule_inside_solve_1d(oracle_lib):
+    """The Section 5.2 rule as the solver applies it, on a 1-D QP whose first
+    ADMM iterate, residuals and normalisers were worked out by hand
+    (tests/golden/rho_rule_1d.txt): after the first check rho-bar becomes
+    3.1434085266297456."""
+    vals = {}
+    with open(os.path.join(GOLDEN, "rho_rule_1d.txt")) as fh:
+        for raw in fh:
+            t = raw.split("#", 1)[0].split()
+            if t:
+                vals[t[0]] = float(t[1])
+    qp = _qp_dense([[vals["P"]]], [vals["q"]], [[vals["A"]]], [vals["l"]], [vals["u"]], "rho1d")
+    r = oracle_lib.solve(qp, scaling_iters=0, sigma=vals["sigma"], rho=vals["rho"], alpha=1.0,
+                         check_every=1, max_iter=2, adaptive_rho=1, polish=0)
+    assert r.rho_updates == int(vals["rho_updates"])
+    assert r.rho_bar == pytest.approx(vals["rho_bar_after"], rel=1e-10)
+
+
 # ---------------------------------------------------------------- invariants
 def test_complementarity_invariant(oracle_lib):
     """Section 3.3: for every k >= 1, z = Pi(v) and y = rho (v - Pi(v)) give
