@@ -3,8 +3,10 @@ infrastructure only; the product library is the gfx950 build of
 paper_1711_08013_amd/build.py).
 
 The library source is compiled as plain C++ against the stand-in runtime in
-tests/simt/include/hip/hip_runtime.h.  Two mechanical edits are made to a
-copy of it: each triple-chevron launch becomes a call of simt::launch with
+tests/simt/include/hip/hip_runtime.h, for an emulated device of
+SIMT_CU_COUNT (default 256) compute units whose occupancy and static LDS per
+kernel are those the gfx950 build of the same source reports.  Two
+mechanical edits are made to a copy of it: each triple-chevron launch becomes a call of simt::launch with
 the kernel call in a lambda, and every array of the device arena gets an
 allocation of its own.  The build uses the host address sanitizer, so every
 device-memory access of the kernels is bounds-checked against the
@@ -135,6 +137,59 @@ const bool simt_bound = [] {
 """
 
 
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+_RES_LINE = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|LDS Size \[bytes/block\]):\s*(\S+)")
+
+
+def gfx950_resources() -> dict:
+    """Registers and static LDS of every kernel, as the gfx950 build of the
+    library reports them (hipcc's kernel-resource-usage remarks, with the
+    product build's code-generation flags): {(name, type): (vgpr, agpr, lds)},
+    type 'f', 'd' or '' for a kernel that is not a template."""
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           "--cuda-device-only", "-c", "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage",
+           os.path.join(CSRC, "api.hip")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stderr[-4000:])
+        raise RuntimeError("gfx950 resource report failed")
+    out, cur = {}, None
+    for line in res.stderr.splitlines():
+        m = _RES_LINE.search(line)
+        if not m:
+            continue
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            mm = re.match(r"_ZN6osqpmi(\d+)", val)
+            if not mm:
+                cur = None
+                continue
+            ln = int(mm.group(1))
+            rest = val[mm.end():]
+            name, rest = rest[:ln], rest[ln:]
+            typ = rest[1] if rest.startswith("I") and rest[1] in "fd" else ""
+            cur = [name, typ, 0, 0, 0]
+            out[(name, typ)] = cur
+        elif cur is not None:
+            idx = {"VGPRs": 2, "AGPRs": 3}.get(key, 4)
+            cur[idx] = int(val)
+    return {k: tuple(v[2:]) for k, v in out.items()}
+
+
+def resource_registrations(res: dict) -> str:
+    """C++ that registers each kernel's gfx950 resources with the stand-in
+    runtime (its occupancy and static-LDS queries read them)."""
+    ctype = {"f": "float", "d": "double"}
+    lines = ["namespace {", "const bool simt_resources_registered = [] {", "  using namespace osqpmi;"]
+    for (name, typ), (vg, ag, lds) in sorted(res.items()):
+        fn = f"{name}<{ctype[typ]}>" if typ else name
+        lines.append(f"  ::simt::register_resources((const void *){fn}, {vg}, {ag}, {lds});")
+    lines += ["  return true;", "}();", "}  // namespace", ""]
+    return "\n".join(lines)
+
+
 def _sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -145,6 +200,7 @@ def _sources_hash() -> str:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode() + fh.read())
     h.update(CLANG.encode() + str(SEPARATE_ARRAYS).encode() + str(WITH_SERVER).encode())
+    h.update(os.environ.get("SIMT_CU_COUNT", "256").encode())
     return h.hexdigest()
 
 
@@ -160,11 +216,16 @@ def build(verbose: bool = False, force: bool = False) -> str:
                 return LIB
     with open(os.path.join(CSRC, "api.hip")) as fh:
         src = translate(fh.read())
+    res = gfx950_resources()
+    if ("solve_wg_kernel", "f") not in res or ("polish_wg_kernel", "d") not in res:
+        raise RuntimeError("resource report lacks the solve or polish kernels")
+    src += resource_registrations(res)
     cpp = os.path.join(OUT_DIR, "api_simt.cpp")
     with open(cpp, "w") as fh:
         fh.write(src)
     tmp = LIB + ".tmp"
     cmd = [CLANG, "-std=c++17", "-O1", "-g", "-fPIC", "-shared",
+           f"-DSIMT_CU_COUNT={int(os.environ.get('SIMT_CU_COUNT', '256'))}",
            "-fsanitize=address", "-fno-omit-frame-pointer",
            "-Wno-unknown-pragmas", "-Wno-unused-command-line-argument",
            "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"),

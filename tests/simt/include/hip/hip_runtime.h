@@ -14,10 +14,15 @@
 //     site; lanes elsewhere are still on a longer path to it, which is the
 //     order in which a wave runs a divergent branch.
 // Threads run in alternating ascending and descending order between
-// synchronisation points.  The workgroups of an ordinary launch run one
-// after another, the last one first (so the highest per-workgroup workspace
-// slot is the one a work queue hands everything to); those of a cooperative
-// launch run side by side, each with its own copy of the LDS section.
+// synchronisation points.  The workgroups of an ordinary launch run in
+// groups of SIMT_SIDE_BY_SIDE (environment, default 4) side by side, taken
+// alternately from the top and the bottom of the grid (so a work queue hands
+// its items to the highest and the lowest per-workgroup workspace slots at
+// once); those of a cooperative launch all run side by side.  Workgroups
+// that run side by side each have their own copy of the LDS section.
+// The emulated device has SIMT_CU_COUNT compute units (build-time, default
+// 256, as on gfx950); occupancy and static LDS size come from the resource
+// usage the gfx950 build reports for each kernel (registered by the build).
 // Device memory is host memory from malloc, so a host address sanitizer
 // sees every device access.
 #pragma once
@@ -271,11 +276,13 @@ inline bool resolve_wave(int base, int end) {
   return true;
 }
 
-// Run nblk workgroups of nt threads side by side (blocks bid0, bid0+1, ...)
-// to completion: one for an ordinary launch, the whole grid for a
-// cooperative one, whose grid barrier spins with s_sleep (a yield here).
-inline void run_blocks(int nblk, int nt, int bid0, int gdim, const std::function<void()> &body) {
+// Run the workgroups `bids` (nt threads each) side by side to completion:
+// a group of an ordinary launch, or the whole grid of a cooperative one,
+// whose grid barrier spins with s_sleep (a yield here).
+inline void run_blocks(const std::vector<int> &bids, int nt, int gdim,
+                       const std::function<void()> &body) {
   Sched &s = S();
+  const int nblk = (int)bids.size();
   constexpr size_t kStack = 1u << 20;
   const int total = nblk * nt;
   s.f.clear();
@@ -321,7 +328,7 @@ inline void run_blocks(int nblk, int nt, int bid0, int gdim, const std::function
         std::memcpy(__start_simt_lds, lds[lds_loaded].data(), lds_bytes);
       }
       s.cur = t;
-      s.bid = bid0 + t / nt;
+      s.bid = bids[t / nt];
       g_tid = (unsigned)(t % nt);
       g_bid = (unsigned)s.bid;
 #ifdef SIMT_ASAN
@@ -351,7 +358,7 @@ inline void run_blocks(int nblk, int nt, int bid0, int gdim, const std::function
         // a barrier reached by only part of the workgroup (others finished)
         // is a divergent barrier: report it
         if (some_done) {
-          std::fprintf(stderr, "simt: barrier with finished threads (block %d)\n", bid0 + b);
+          std::fprintf(stderr, "simt: barrier with finished threads (block %d)\n", bids[b]);
           std::abort();
         }
         for (int t = b0; t < b1; ++t) s.f[t].state = RUN;
@@ -360,7 +367,7 @@ inline void run_blocks(int nblk, int nt, int bid0, int gdim, const std::function
     }
     if (all_done) break;
     if (!ran && !progress) {
-      std::fprintf(stderr, "simt: deadlock (blocks %d..%d)\n", bid0, bid0 + nblk - 1);
+      std::fprintf(stderr, "simt: deadlock (%d blocks from %d)\n", nblk, bids[0]);
       std::abort();
     }
   }
@@ -396,11 +403,33 @@ inline void arm_watchdog() {
   alarm((unsigned)secs);
 }
 
+// workgroups of an ordinary launch that run side by side
+inline int side_by_side() {
+  static const int k = [] {
+    const char *e = std::getenv("SIMT_SIDE_BY_SIDE");
+    const int v = e ? std::atoi(e) : 4;
+    return v < 1 ? 1 : v;
+  }();
+  return k;
+}
+
 template <class F>
 inline void launch(dim3 grid, dim3 block, F &&kernel_call) {
   arm_watchdog();
   const std::function<void()> body = [&]() { kernel_call(); };
-  for (int b = (int)grid.x - 1; b >= 0; --b) run_blocks(1, (int)block.x, b, (int)grid.x, body);
+  // blocks alternately from the top and the bottom of the grid
+  const int g = (int)grid.x;
+  std::vector<int> order;
+  for (int lo = 0, hi = g - 1; lo <= hi; ++lo, --hi) {
+    order.push_back(hi);
+    if (lo != hi) order.push_back(lo);
+  }
+  const int k = side_by_side();
+  for (size_t i = 0; i < order.size(); i += (size_t)k) {
+    const std::vector<int> ids(order.begin() + (long)i,
+                               order.begin() + (long)std::min(order.size(), i + (size_t)k));
+    run_blocks(ids, (int)block.x, g, body);
+  }
   if (std::getenv("SIMT_WATCHDOG")) alarm(0);
 }
 
@@ -408,8 +437,31 @@ template <class F>
 inline void launch_cooperative(dim3 grid, dim3 block, F &&kernel_call) {
   arm_watchdog();
   const std::function<void()> body = [&]() { kernel_call(); };
-  run_blocks((int)grid.x, (int)block.x, 0, (int)grid.x, body);
+  std::vector<int> ids((size_t)grid.x);
+  for (int b = 0; b < (int)grid.x; ++b) ids[(size_t)b] = b;
+  run_blocks(ids, (int)block.x, (int)grid.x, body);
   if (std::getenv("SIMT_WATCHDOG")) alarm(0);
+}
+
+// Resource usage of each kernel as the gfx950 build reports it (registered
+// by the host build): registers per lane and static LDS per workgroup.
+struct KernelRes {
+  const void *fn;
+  int vgpr, agpr, lds;
+};
+inline std::vector<KernelRes> &kernel_resources() {
+  static std::vector<KernelRes> r;
+  return r;
+}
+inline bool register_resources(const void *fn, int vgpr, int agpr, int lds) {
+  kernel_resources().push_back({fn, vgpr, agpr, lds});
+  return true;
+}
+inline const KernelRes &resources_of(const void *fn) {
+  for (const KernelRes &k : kernel_resources())
+    if (k.fn == fn) return k;
+  std::fprintf(stderr, "simt: no resource record for a kernel\n");
+  std::abort();
 }
 
 inline Lane &me() { return S().f[S().cur].lane; }
@@ -511,28 +563,49 @@ struct hipKernelNodeParams {
   unsigned sharedMemBytes;
 };
 
-// workgroups the emulated device runs side by side (the grid size of a
-// work-queue launch)
+// compute units of the emulated device (gfx950: 256)
 #ifndef SIMT_CU_COUNT
-#define SIMT_CU_COUNT 3
+#define SIMT_CU_COUNT 256
 #endif
 
 inline hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+// SIMT_CUS (environment) overrides the build-time count, for the runs of a
+// cooperative launch, whose whole grid (one workgroup per CU) runs side by side
+inline int simt_cu_count() {
+  static const int n = [] {
+    const char *e = std::getenv("SIMT_CUS");
+    const int v = e ? std::atoi(e) : 0;
+    return v > 0 ? v : SIMT_CU_COUNT;
+  }();
+  return n;
+}
 inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) {
-  p->multiProcessorCount = SIMT_CU_COUNT;
+  p->multiProcessorCount = simt_cu_count();
   p->sharedMemPerBlock = 160 * 1024;
   p->maxSharedMemoryPerMultiProcessor = 160 * 1024;
   return hipSuccess;
 }
 inline hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) { *v = 100000; return hipSuccess; }
-inline hipError_t hipFuncGetAttributes(hipFuncAttributes *a, const void *) {
-  a->sharedSizeBytes = 0;
+inline hipError_t hipFuncGetAttributes(hipFuncAttributes *a, const void *fn) {
+  a->sharedSizeBytes = (size_t)::simt::resources_of(fn).lds;
   return hipSuccess;
 }
+// Workgroups of `block` threads one CU holds at once, from the kernel's
+// registers and LDS: four SIMDs, each with 512 registers per lane shared by
+// its waves (allocated in granules of 8, vector then accumulation registers)
+// and at most 8 waves; a workgroup's waves spread over the four SIMDs;
+// 160 KiB of LDS per CU.
 template <class F>
-inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, F, int, size_t) {
-  *n = 1;
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, F fn, int block, size_t dyn) {
+  const ::simt::KernelRes &r = ::simt::resources_of((const void *)fn);
+  const int regs = ((r.vgpr + 7) / 8) * 8 + ((r.agpr + 7) / 8) * 8;
+  const int waves_simd = std::min(8, regs > 0 ? 512 / regs : 8);
+  const int waves = (block + 63) / 64, per_simd = (waves + 3) / 4;
+  int wg = per_simd > 0 ? waves_simd / per_simd : 0;
+  const size_t lds = (size_t)r.lds + dyn;
+  if (lds > 0) wg = std::min(wg, (int)((160u * 1024u) / lds));
+  *n = std::max(0, wg);
   return hipSuccess;
 }
 inline hipError_t hipMalloc(void **p, size_t bytes) {

@@ -55,9 +55,12 @@ def simt_lib():
 def test_kernels_on_cpu_match_oracle(simt_lib):
     env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
                SIMT_WATCHDOG="300")
+    # the cooperative launch runs its whole grid (one workgroup per CU) side
+    # by side: that group runs on an emulated device of three CUs
     procs = [subprocess.Popen([sys.executable, os.path.join(SIMT, "runner.py"), *g],
                               stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
-                              env=env, cwd=ROOT) for g in GROUPS]
+                              env=dict(env, SIMT_CUS="3") if g == ["grid"] else env, cwd=ROOT)
+             for g in GROUPS]
     outs = []
     for p in procs:
         try:
