@@ -1,6 +1,8 @@
-"""Host-side logic of bench.py, on the CPU: the one-GPU guard, the byte model
-of the solve kernel on a hand-counted instance, and the rule that ties the
-stored counter traffic to the kernel sources and the launch shape."""
+"""Host-side logic of bench.py, on the CPU: the one-GPU guard, the two byte
+models (the algorithmic bytes of the method and the bytes of this
+implementation's passes) on a hand-counted instance, the rule that ties the
+stored counter traffic to the kernel sources and the launch shape, the error
+report against the oracle, the serving statistics and the rate bisection."""
 from __future__ import annotations
 
 import os
@@ -36,7 +38,22 @@ def _tiny():
     return QP(P, np.zeros(3), A, -np.ones(4), np.ones(4), name="tiny")
 
 
-def test_byte_model_hand_count():
+def test_algorithmic_bytes_hand_count():
+    """Per PCG iteration 16a + 8p + 4(12n + 4m); per ADMM step one more such
+    pass plus 4(5n + 12m); per check 12(2a + p) + 8(6n + 6m); no factor."""
+    qp = _tiny()
+    n, m, a, p = 3, 4, 7, 5
+    pcg_b = 16 * a + 8 * p + 4 * (12 * n + 4 * m)          # 112 + 40 + 208 = 360
+    assert pcg_b == 360
+    for path in (1, 2, 3):
+        info = {"iter": 50, "pcg_iter": 80, "rho_updates": 1, "linsys": path}
+        want = (80 + 50) * 360 + 50 * 4 * (5 * n + 12 * m) + 2 * (12 * (2 * a + p) + 8 * (6 * n + 6 * m))
+        assert bench.algorithmic_bytes([qp], [info]) == want
+    info = {"iter": 26, "pcg_iter": 26, "rho_updates": 0, "linsys": 3}
+    assert bench.s8d_bytes(qp, info) == 52 * 360 + 26 * 4 * 63 + 2 * (12 * 19 + 8 * 42)
+
+
+def test_path_bytes_hand_count():
     qp = _tiny()
     n, m, a, p, am, R = 3, 4, 7, 5, 5, 2
     e = 8                              # FP32 value + int32 index
@@ -46,17 +63,17 @@ def test_byte_model_hand_count():
     pcg_b = e * (2 * a + p) + 4 * (2 * n + m) + 4 * (5 * n + 2 * m) + 16 * n
     # Jacobi: PCG products only
     info = {"iter": it, "pcg_iter": pcg, "rho_updates": rho_up, "linsys": 1}
-    assert bench.algorithmic_bytes([qp], [info]) == admm + pcg * pcg_b + chk
+    assert bench.path_bytes([qp], [info]) == admm + pcg * pcg_b + chk
     # dense factor: applies once per ADMM step and per extra inner step
     info["linsys"] = 2
     applies = (it + (pcg - it)) * (4 * n * n + 8 * n)
     fact = (1 + rho_up) * 3 * 4 * n * n
-    assert bench.algorithmic_bytes([qp], [info]) == admm + pcg * pcg_b + applies + chk + fact
+    assert bench.path_bytes([qp], [info]) == admm + pcg * pcg_b + applies + chk + fact
     # low-rank direct step: one apply per counted inner step, no PCG products
     info["linsys"] = 3
     work = pcg * (e * (am + a) + 8 * (R * R + 4 * n + 2 * m))
     fact = (1 + rho_up) * (8 * (2 * R * n + R * R) + e * am)
-    assert bench.algorithmic_bytes([qp], [info]) == admm + work + chk + fact
+    assert bench.path_bytes([qp], [info]) == admm + work + chk + fact
 
 
 def test_stored_traffic_needs_matching_sources_and_shape(monkeypatch, tmp_path):
@@ -90,3 +107,56 @@ def test_kernel_hash_covers_the_device_headers():
         with open(os.path.join(csrc, f)) as fh:
             todo += [l.split('"')[1] for l in fh if l.startswith('#include "')]
     assert seen <= set(bench.KERNEL_SOURCES), seen - set(bench.KERNEL_SOURCES)
+
+
+def test_error_report_against_oracle():
+    """Status match, objective error, eps-scaled residuals and the x error
+    (P diagonal and positive here) computed from the results as returned."""
+    import oracle
+    import qpgen
+    qps = [qpgen.box_qp(np.array([1.0, 2.0]), np.array([-1.0, 1.0]), -np.ones(2), np.ones(2))
+           for _ in range(3)]
+    refs = [oracle.solve(q) for q in qps]
+    good = (refs[0].x, refs[0].y, {"status_name": "solved", "obj_val": refs[0].obj_val})
+    off = (refs[1].x + 1e-2, refs[1].y, {"status_name": "solved", "obj_val": refs[1].obj_val * 1.01})
+    wrong = (refs[2].x, refs[2].y, {"status_name": "max_iter_reached", "obj_val": 0.0})
+    rep = bench.error_report(qps, [good, off, wrong], refs)
+    assert rep["status_match"] == 2 and rep["both_solved"] == 2
+    assert abs(rep["max_rel_obj_err"] - 0.01 * abs(refs[1].obj_val) / max(1.0, abs(refs[1].obj_val))) < 1e-12
+    assert rep["obj_err_above_1e-3"] == 1
+    assert abs(rep["max_rel_x_err_p_definite"] - 1e-2 / max(1.0, np.max(np.abs(refs[1].x)))) < 1e-12
+    # the perturbed point leaves the box by 1e-2: it fails the eps test
+    assert rep["max_eps_scaled_prim"] > 1.0
+    rep = bench.error_report(qps[:1], [good], refs[:1])
+    assert rep["max_eps_scaled_prim"] <= 1.0 + 1e-9 and rep["max_eps_scaled_dual"] <= 1.0 + 1e-9
+
+
+def test_latency_order_statistics_skip_warmup():
+    arrivals = [0.1, 0.5, 1.0, 1.2, 1.5, 2.0]
+    lats = [9.0, 9.0, 0.001, 0.002, 0.003, 0.004]
+    st = bench.latency_stats(arrivals, lats, warmup_s=1.0)
+    assert st["counted"] == 4
+    assert st["p50_ms"] == 2.0          # 2nd of 4 (ceil(0.5 * 4) = 2)
+    assert st["p99_ms"] == 4.0          # 4th of 4
+    assert bench.latency_stats(arrivals, lats, warmup_s=5.0) is None
+
+
+def test_sustainable_rate_bisection():
+    calls = []
+
+    def ok(r):
+        calls.append(r)
+        return r <= 300.0
+
+    r = bench.bisect_rate(ok, 25.0, 2000.0, 12)
+    assert 290.0 <= r <= 300.0 and calls[0] == 2000.0
+    assert bench.bisect_rate(lambda r: True, 25.0, 2000.0, 5) == 2000.0
+    assert bench.sustainable({"drain_s": 0.2, "throughput_qps": 950.0}, 1000.0)
+    assert not bench.sustainable({"drain_s": 2.0, "throughput_qps": 950.0}, 1000.0)
+    assert not bench.sustainable({"drain_s": 0.2, "throughput_qps": 500.0}, 1000.0)
+
+
+def test_host_threads_capped():
+    assert 1 <= bench.host_threads() <= 16
+    assert bench.host_threads(cap=2) <= 2
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
