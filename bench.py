@@ -101,14 +101,19 @@ def path_bytes(qps, infos, value_bytes=4, check_every=CHECK_EVERY):
                        update pass A    -> e a + 8 (3n + 9m)
       low-rank path  : one direct apply per iteration (counted in pcg_iter)
                        -> e (a_m + a) + 8 (R^2 + 4n + 2m); no PCG products
+      band path      : one direct step per iteration (counted in pcg_iter),
+                       each sweep over the nonzero triangles of the FP64
+                       tiles -> 16 nb n + 8 (3n); no PCG products
       dense path     : PCG iterations e (2a + p) + 4 (2n + m) + vb (5n + 2m) + 16n,
                        applies (ADMM iterations + inner iterations beyond the
                        first) vb n^2 + 2 vb n
       Jacobi path    : PCG iterations as above, no applies
       check (FP64, every 25 iterations): 12 (2a + p) + 8 (6n + 6m)
       factorisation (1 + rho updates): low-rank 8 (2 R n + R^2) + e a_m;
+                                       band 16 nb n + e (a + p);
                                        dense 3 vb n^2
-    """
+    The band block size nb is bounded by 64 (the value used here; the
+    ordering usually gives 56 on the MPC workload)."""
     vb = value_bytes
     e = 4 + vb
     total = 0.0
@@ -121,6 +126,10 @@ def path_bytes(qps, infos, value_bytes=4, check_every=CHECK_EVERY):
         if path == 3:
             work = pcg * (e * (am + a) + 8 * (R * R + 4 * n + 2 * m))
             fact_b = 8 * (2 * R * n + R * R) + e * am
+        elif path == 4:
+            nb = 64
+            work = pcg * (16 * nb * n + 8 * 3 * n)
+            fact_b = 16 * nb * n + e * (a + p)
         elif path == 2:
             work = pcg * pcg_b + (it + max(0, pcg - it)) * (vb * n * n + 2 * vb * n)
             fact_b = 3 * vb * n * n

@@ -55,13 +55,22 @@ typedef double osqp_float;
 #define OSQP_PRECISION_FP32_MIXED 1 /* SpMV/PCG/updates in float; scaling,
                                        checks, certificates, polish in double */
 #define OSQP_LINSYS_AUTO 0          /* low-rank form (P diagonal, few multi-   */
-                                    /* entry rows of A), else the dense factor */
-                                    /* for n <= 2500, else Jacobi PCG          */
+                                    /* entry rows of A), else the band factor  */
+                                    /* (half-bandwidth <= 64 after ordering),  */
+                                    /* else the dense factor for n <= 2500,    */
+                                    /* else Jacobi PCG                         */
 #define OSQP_LINSYS_PCG 1           /* reduced system, Section 3.1 indirect   */
 #define OSQP_LINSYS_DENSE 2         /* dense Cholesky of the reduced matrix   */
 #define OSQP_LINSYS_LOWRANK 3       /* P diagonal, few multi-entry rows of A:  */
                                     /* Woodbury form of the reduced matrix,    */
-                                    /* else as AUTO                            */
+                                    /* else as AUTO (the same order as AUTO)   */
+#define OSQP_LINSYS_BAND 4          /* block-tridiagonal Cholesky factor of    */
+                                    /* the reduced matrix after a reverse      */
+                                    /* Cuthill-McKee ordering (Section 3.1's   */
+                                    /* direct method on the reduced system),   */
+                                    /* where the half-bandwidth is <= 64 and   */
+                                    /* n <= 8192, in preference to the low-   */
+                                    /* rank form; else as AUTO                 */
 
 /* Compressed sparse rows.  indptr has nrows+1 entries, indptr[0] = 0,
  * non-decreasing, indptr[nrows] = nnz; each row's column indices strictly
@@ -93,7 +102,8 @@ typedef struct {
   osqp_float eps_prim_inf, eps_dual_inf;  /* Section 3.4, default 1e-4       */
   osqp_float delta;        /* polish regularisation (Section 4), 1e-6        */
   osqp_float time_limit;   /* seconds of solve time, 0 = none                */
-  osqp_float pcg_tol_frac; /* inner PCG tolerance factor, default 0.15        */
+  osqp_float pcg_tol_frac; /* inner PCG tolerance factor (Jacobi path),      */
+                           /* default 1e-3                                   */
   osqp_int max_iter;       /* default 4000                                   */
   osqp_int check_every;    /* termination-check interval, default 25         */
   osqp_int scaling_iters;  /* Ruiz passes (Section 5.1), default 10          */
@@ -117,7 +127,8 @@ typedef struct {
   osqp_int rho_updates;
   osqp_int polish_status;  /* 1 accepted, -1 rejected, 0 not run            */
   osqp_int linsys;         /* reduced-system path assigned at setup:         */
-                           /* OSQP_LINSYS_PCG (Jacobi), _DENSE or _LOWRANK   */
+                           /* OSQP_LINSYS_PCG (Jacobi), _DENSE, _LOWRANK or  */
+                           /* _BAND                                          */
   osqp_float obj_val;      /* 1/2 x'Px + q'x on the original data (FP64)    */
   osqp_float prim_res, dual_res, eps_prim, eps_dual; /* unscaled, FP64, Sections 3.4/5.1 */
   osqp_float rho_bar;      /* final rho-bar                                  */
@@ -146,6 +157,21 @@ osqp_int osqp_set_default_settings(osqp_settings *s);
 
 /* Human-readable name of an error code (static storage). */
 const char *osqp_error_string(osqp_int code);
+
+/* Device memory for the handles created after this call comes from
+ * alloc(bytes, ctx) and goes back through free_fn(ptr, ctx) -- for instance a
+ * framework's caching allocator, so that the solver's memory is counted and
+ * reused with the caller's own.  alloc returns device memory of the current
+ * device, aligned to at least 256 bytes, or NULL on failure (the setup then
+ * returns OSQP_ERR_ALLOC).  Both NULL restores hipMalloc / hipFree.  Each
+ * handle keeps the pair it was created with until its cleanup, which waits
+ * for the handle's stream before freeing.  Callable from any thread; calls
+ * take effect for setups that start after them.  OSQP_ERR_SETTINGS when only
+ * one of the two is NULL.  (No passage of the paper defines this call: it is
+ * an interface for callers that manage device memory themselves.) */
+typedef void *(*osqp_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*osqp_free_fn)(void *ptr, void *ctx);
+osqp_int osqp_set_allocator(osqp_alloc_fn alloc, osqp_free_fn free_fn, void *ctx);
 
 /* Number of visible HIP devices (0 when none), for callers that must gate. */
 osqp_int osqp_device_count(void);

@@ -22,11 +22,11 @@ ERRORS = {0: "ok", 1: "dim", 2: "csr", 3: "p_not_upper", 4: "data_nonfinite", 5:
           6: "settings", 7: "alloc", 8: "budget", 9: "device", 10: "not_setup",
           11: "index", 12: "no_device", 13: "unsupported"}
 PRECISION = {"fp64": 0, "fp32": 1}
-LINSYS = {"auto": 0, "pcg": 1, "dense": 2, "lowrank": 3}
+LINSYS = {"auto": 0, "pcg": 1, "dense": 2, "lowrank": 3, "band": 4}
 
 # every function the header declares (the CPU tests check the exports)
 EXPORTS = [
-    "osqp_set_default_settings", "osqp_error_string", "osqp_device_count",
+    "osqp_set_default_settings", "osqp_error_string", "osqp_set_allocator", "osqp_device_count",
     "osqp_device_info", "osqp_setup",
     "osqp_solve", "osqp_update_vectors", "osqp_warm_start", "osqp_update_matrices",
     "osqp_get_solution",
@@ -85,6 +85,12 @@ class _Tuning(ctypes.Structure):
                [(k, ctypes.c_double) for k in ("default_ms", "best_ms")]
 
 
+# device-memory callbacks of osqp_set_allocator: alloc(bytes, ctx) -> pointer,
+# free(pointer, ctx)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None   # the installed callbacks, kept alive while installed
+
 _lib = None
 
 
@@ -117,7 +123,47 @@ def _configure(L: ctypes.CDLL) -> ctypes.CDLL:
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.osqp_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.osqp_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, ctypes.c_void_p]
     return L
+
+
+def set_allocator(alloc=None, free=None):
+    """Device memory of the handles created from now on comes from
+    alloc(nbytes) -> int address and goes back through free(address)
+    (osqp_set_allocator); no arguments restore hipMalloc / hipFree."""
+    global _allocator_refs
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check(lib().osqp_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "osqp_set_allocator")
+        _allocator_refs = None
+        return
+
+    def _a(nbytes, _ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:   # an exception must not cross the C boundary
+            return None
+
+    def _f(ptr, _ctx):
+        try:
+            free(int(ptr))
+        except Exception:
+            pass
+
+    refs = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _check(lib().osqp_set_allocator(refs[0], refs[1], None), "osqp_set_allocator")
+    _allocator_refs = refs
+
+
+def use_torch_allocator(device: int = 0):
+    """Device memory from PyTorch's caching allocator (on `device`, torch's
+    current stream), so the solver's memory is counted and reused with the
+    caller's tensors; torch.cuda.current_stream().cuda_stream can be passed as
+    the `stream` setting to run on torch's stream as well."""
+    import torch
+    set_allocator(lambda nb: torch.cuda.caching_allocator_alloc(nb, device),
+                  torch.cuda.caching_allocator_delete)
 
 
 def device_count() -> int:

@@ -8,12 +8,14 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
 
 #include "osqp_mi.h"
 #include "kernels.h"
+#include "ordering.h"
 
 using namespace osqpmi;
 
@@ -27,6 +29,8 @@ constexpr double kDenseBudget = 48e9;   // bytes of dense factors per batch
 constexpr int kLowRankMaxR = 2048;      // most multi-entry rows of a low-rank QP
 constexpr int64_t kLowRankMaxG = int64_t(1) << 23;   // doubles of G scratch per workgroup
 constexpr double kLowRankBudget = 32e9;   // bytes of low-rank blocks per batch
+constexpr int kBandMaxNB = 64;           // largest block of the block-tridiagonal factor
+constexpr int kBandMaxN = kStage;        // its solve keeps the permuted vector in LDS
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -87,7 +91,7 @@ int check_settings(const osqp_settings &s) {
     return OSQP_ERR_SETTINGS;
   if (s.precision != OSQP_PRECISION_FP64 && s.precision != OSQP_PRECISION_FP32_MIXED)
     return OSQP_ERR_SETTINGS;
-  if (s.linsys < 0 || s.linsys > 3) return OSQP_ERR_SETTINGS;
+  if (s.linsys < 0 || s.linsys > 4) return OSQP_ERR_SETTINGS;
   if (s.block_size != 0 && (s.block_size < 64 || s.block_size > kMaxBlock || s.block_size % 64))
     return OSQP_ERR_SETTINGS;
   return OSQP_OK;
@@ -99,6 +103,40 @@ int pow2_lanes(double avg, int div) {
   int L = 1;
   while (L < 64 && double(div) * L < avg) L <<= 1;
   return L;
+}
+
+// ---------------------------------------------------------------------------
+// device allocations: hipMalloc / hipFree unless osqp_set_allocator installed
+// a pair; every handle keeps the pair it was created with, so its frees go
+// where its allocations came from
+// ---------------------------------------------------------------------------
+struct DevAllocator {
+  osqp_alloc_fn alloc = nullptr;
+  osqp_free_fn free = nullptr;
+  void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;
+
+DevAllocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+template <class P>
+hipError_t dev_alloc(const DevAllocator &a, P **p, size_t bytes) {
+  if (!a.alloc) {
+    const hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    if (e != hipSuccess) *p = nullptr;   // nothing for destroy() to free
+    return e;
+  }
+  void *q = a.alloc(bytes ? bytes : 1, a.ctx);
+  *p = static_cast<P *>(q);
+  return q ? hipSuccess : hipErrorInvalidValue;
+}
+void dev_free(const DevAllocator &a, void *p) {
+  if (!p) return;
+  if (a.free) a.free(p, a.ctx);
+  else (void)hipFree(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,6 +161,7 @@ struct Arena {
 // the batch object
 // ---------------------------------------------------------------------------
 struct osqp_batch {
+  DevAllocator alloc;   // where this handle's device memory comes from
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -137,6 +176,9 @@ struct osqp_batch {
   int64_t lr_total = 0, lws_stride = 0;   // low-rank blocks / G scratch per workgroup
   int lws_slots = 0;
   std::vector<int> mrows;
+  // band path: the ordering of every band QP (position -> variable and its
+  // inverse, in the n-vector layout; identity elsewhere)
+  std::vector<int> bperm_h, biperm_h;
   // host staging of the inputs that change through the parametric API
   std::vector<double> q_raw, l_raw, u_raw;
   std::vector<double> xws_h, yws_h;   // warm-start staging
@@ -291,6 +333,8 @@ void fill_batch_ptrs(Batch<T> &B, osqp_batch *b, Arena &ar, bool alias64) {
   B.yo = ar.take<double>(sm);
   B.zo = ar.take<double>(sm);
   B.mrows = ar.take<int>(std::max<int64_t>(1, b->mr_total));
+  B.bperm = ar.take<int>(sn);
+  B.biperm = ar.take<int>(sn);
   B.dmat = b->dense_total > 0 ? ar.take<T>(b->dense_total) : nullptr;
   B.dws = b->dense_total > 0 ? ar.take<T>((size_t)b->dws_stride * b->dws_slots) : nullptr;
   B.dws_stride = b->dws_stride;
@@ -389,8 +433,8 @@ int launch_subset(osqp_batch *b, const std::vector<int> &idx, const std::vector<
   Batch<T> &B = batch_of<T>(b);
   B.set = b->dev_settings();
   if (!b->d_subset) {
-    if (hipMalloc(&b->d_subset, sizeof(int) * b->nq) != hipSuccess ||
-        hipMalloc(&b->d_subset_polish, sizeof(int) * b->nq) != hipSuccess)
+    if (dev_alloc(b->alloc, &b->d_subset, sizeof(int) * b->nq) != hipSuccess ||
+        dev_alloc(b->alloc, &b->d_subset_polish, sizeof(int) * b->nq) != hipSuccess)
       return OSQP_ERR_ALLOC;
   }
   // the lists are staged in the batch's own host buffers, which stay
@@ -542,15 +586,18 @@ int fetch_results(osqp_batch *b) {
 
 void destroy(osqp_batch *b) {
   if (!b) return;
-  if (b->arena) (void)hipFree(b->arena);
-  if (b->d_pws) (void)hipFree(b->d_pws);
-  if (b->d_polish) (void)hipFree(b->d_polish);
-  if (b->d_small) (void)hipFree(b->d_small);
-  if (b->d_subset) (void)hipFree(b->d_subset);
-  if (b->d_subset_polish) (void)hipFree(b->d_subset_polish);
-  if (b->d_big) (void)hipFree(b->d_big);
-  if (b->d_partials) (void)hipFree(b->d_partials);
-  if (b->d_bar) (void)hipFree(b->d_bar);
+  // an allocator other than hipFree may hand the memory out again at once:
+  // the handle's work must be done first
+  if (b->stream && b->alloc.free) (void)hipStreamSynchronize(b->stream);
+  dev_free(b->alloc, b->arena);
+  dev_free(b->alloc, b->d_pws);
+  dev_free(b->alloc, b->d_polish);
+  dev_free(b->alloc, b->d_small);
+  dev_free(b->alloc, b->d_subset);
+  dev_free(b->alloc, b->d_subset_polish);
+  dev_free(b->alloc, b->d_big);
+  dev_free(b->alloc, b->d_partials);
+  dev_free(b->alloc, b->d_bar);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
   if (b->ev2) (void)hipEventDestroy(b->ev2);
@@ -579,6 +626,7 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
   const double t0 = now_s();
   osqp_batch *b = new (std::nothrow) osqp_batch();
   if (!b) return OSQP_ERR_ALLOC;
+  b->alloc = current_allocator();
   b->set = s;
   b->nq = count;
   b->fp64 = (s.precision == OSQP_PRECISION_FP64);
@@ -714,14 +762,41 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     const int64_t g = (int64_t)R * ((p.n + 7) & ~7);
     const bool fits = pdiag && R >= 1 && 2 * R <= p.n && R <= kLowRankMaxR && g <= kLowRankMaxG;
     b->desc[k].plr = fits ? 1 : 0;
-    lowrank[k] = fits && (s.linsys == OSQP_LINSYS_AUTO || s.linsys == OSQP_LINSYS_LOWRANK);
+    lowrank[k] = fits && s.linsys != OSQP_LINSYS_PCG && s.linsys != OSQP_LINSYS_DENSE;
+  }
+  // band eligibility (the symbolic step of the band factor): a reverse
+  // Cuthill-McKee ordering of P + A'A whose half-bandwidth is at most
+  // kBandMaxNB, and a block-tridiagonal factor smaller than the dense one
+  std::vector<int> band_nb(count, 0);
+  b->bperm_h.assign(b->sum_n, 0);
+  b->biperm_h.assign(b->sum_n, 0);
+  // (AUTO and LOWRANK take the low-rank form first where it applies, BAND
+  // the band factor)
+  if (s.linsys != OSQP_LINSYS_PCG && s.linsys != OSQP_LINSYS_DENSE) {
+    std::vector<int> perm;
+    for (int k = 0; k < count; ++k) {
+      const osqp_problem &p = probs[k];
+      if ((lowrank[k] && s.linsys != OSQP_LINSYS_BAND) || p.n < 2 || p.n > kBandMaxN) continue;
+      const int bw = rcm_ordering(p, kBandMaxNB + 1, perm);
+      if (bw < 0) continue;
+      const int nb = std::max(8, (bw + 7) & ~7);
+      const int64_t nblk = (p.n + nb - 1) / nb;
+      if (nb > kBandMaxNB || 2 * nblk * nb * nb > (int64_t)p.n * p.n / 2) continue;
+      band_nb[k] = nb;
+      lowrank[k] = 0;
+      const int64_t xo = b->desc[k].xo;
+      for (int i = 0; i < p.n; ++i) {
+        b->bperm_h[xo + i] = perm[i];
+        b->biperm_h[xo + perm[i]] = i;
+      }
+    }
   }
   for (int k = 0; k < count; ++k) {
-    // a QP with an exact preconditioner (dense or low-rank) stays on a
+    // a QP with an exact preconditioner (dense, band or low-rank) stays on a
     // workgroup: its PCG converges in a step or two, and the whole-grid team
     // would pay a grid barrier per pass
     const int n = probs[k].n;
-    const bool dense_ok = lowrank[k] ||
+    const bool dense_ok = lowrank[k] || band_nb[k] > 0 ||
                           (s.linsys == OSQP_LINSYS_DENSE && n <= kDenseMaxN) ||
                           (s.linsys != OSQP_LINSYS_PCG && n <= kDenseAutoN);
     const bool big = !dense_ok && cost[k] >= (int64_t)400000 &&
@@ -761,6 +836,21 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
           continue;
         }
       }
+      if (band_nb[k] > 0) {
+        // the band block (FP64 factor and residual) lives in the low-rank
+        // arena, its formation scratch in the low-rank workspace
+        const int nb = band_nb[k];
+        const int64_t elems = band_layout(n, nb).total;
+        if (lbytes + 8.0 * (double)elems <= kLowRankBudget) {
+          lbytes += 8.0 * (double)elems;
+          d.dense = 3;
+          d.dld = nb;
+          d.dense_off = b->lr_total;
+          b->lr_total += elems;
+          gmax = std::max(gmax, band_scratch(nb));
+          continue;
+        }
+      }
       if (want) cand.push_back(k);
     }
     if (b->lr_total > 0) {
@@ -793,7 +883,7 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
 
   const bool alias = b->fp64;
   b->arena_bytes = b->fp64 ? arena_bytes_for<double>(b, true) : arena_bytes_for<float>(b, false);
-  if (hipMalloc(&b->arena, b->arena_bytes) != hipSuccess) {
+  if (dev_alloc(b->alloc, &b->arena, b->arena_bytes) != hipSuccess) {
     b->arena = nullptr;
     destroy(b);
     return OSQP_ERR_ALLOC;
@@ -908,21 +998,23 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     ok &= up((void *)B.u_raw, b->u_raw.data(), sizeof(double) * sm);
     ok &= up((void *)B.is_eq, b->is_eq.data(), sm);
     ok &= up((void *)B.mrows, b->mrows.data(), sizeof(int) * b->mrows.size());
+    ok &= up((void *)B.bperm, b->bperm_h.data(), sizeof(int) * sn);
+    ok &= up((void *)B.biperm, b->biperm_h.data(), sizeof(int) * sn);
     return ok;
   };
   bool ok = b->fp64 ? upload(b->bd) : upload(b->bf);
   if (!ok) { destroy(b); return OSQP_ERR_DEVICE; }
 
   if (!b->big_list.empty()) {
-    if (hipMalloc(&b->d_partials, sizeof(double) * 2 * kRedSlots * b->grid_coop) != hipSuccess ||
-        hipMalloc(&b->d_bar, sizeof(GridBarrier)) != hipSuccess) {
+    if (dev_alloc(b->alloc, &b->d_partials, sizeof(double) * 2 * kRedSlots * b->grid_coop) != hipSuccess ||
+        dev_alloc(b->alloc, &b->d_bar, sizeof(GridBarrier)) != hipSuccess) {
       destroy(b);
       return OSQP_ERR_ALLOC;
     }
   }
   // lists
-  if (hipMalloc(&b->d_small, sizeof(int) * std::max<size_t>(1, b->small_list.size())) != hipSuccess ||
-      hipMalloc(&b->d_big, sizeof(int) * std::max<size_t>(1, b->big_list.size())) != hipSuccess) {
+  if (dev_alloc(b->alloc, &b->d_small, sizeof(int) * std::max<size_t>(1, b->small_list.size())) != hipSuccess ||
+      dev_alloc(b->alloc, &b->d_big, sizeof(int) * std::max<size_t>(1, b->big_list.size())) != hipSuccess) {
     destroy(b);
     return OSQP_ERR_ALLOC;
   }
@@ -954,9 +1046,8 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       b->pws_stride = (stride + 7) & ~int64_t(7);   // 64-byte slot bases (16-byte loads)
       b->polish_slots = std::max(1, std::min((int)b->polish_list.size(),
                                              prop.multiProcessorCount));
-      if (hipMalloc(&b->d_pws, sizeof(double) * b->pws_stride * b->polish_slots) != hipSuccess ||
-          hipMalloc(&b->d_polish, sizeof(int) * b->polish_list.size()) != hipSuccess) {
-        b->d_pws = nullptr;
+      if (dev_alloc(b->alloc, &b->d_pws, sizeof(double) * b->pws_stride * b->polish_slots) != hipSuccess ||
+          dev_alloc(b->alloc, &b->d_polish, sizeof(int) * b->polish_list.size()) != hipSuccess) {
         destroy(b);
         return OSQP_ERR_ALLOC;
       }
@@ -983,7 +1074,9 @@ void fill_info(const osqp_batch *b, int k, osqp_info *info) {
   info->polish_status = S.polish_status;
   {
     const int dk = b->desc[k].dense;
-    info->linsys = dk == 1 ? OSQP_LINSYS_DENSE : (dk == 2 ? OSQP_LINSYS_LOWRANK : OSQP_LINSYS_PCG);
+    info->linsys = dk == 1 ? OSQP_LINSYS_DENSE
+                 : dk == 2 ? OSQP_LINSYS_LOWRANK
+                 : dk == 3 ? OSQP_LINSYS_BAND : OSQP_LINSYS_PCG;
   }
   info->obj_val = S.obj;
   info->prim_res = S.prim_res;
@@ -1019,7 +1112,7 @@ osqp_int osqp_set_default_settings(osqp_settings *s) {
   s->eps_dual_inf = 1e-4;
   s->delta = 1e-6;
   s->time_limit = 0.0;
-  s->pcg_tol_frac = 0.15;
+  s->pcg_tol_frac = 1e-3;
   s->max_iter = 4000;
   s->check_every = 25;
   s->scaling_iters = 10;
@@ -1068,6 +1161,15 @@ osqp_int osqp_device_info(osqp_int *cu_count, osqp_int *lds_per_block, osqp_int 
     (void)hipDeviceGetAttribute(&w, hipDeviceAttributeWallClockRate, dev);
     *wall_khz = w;
   }
+  return OSQP_OK;
+}
+
+osqp_int osqp_set_allocator(osqp_alloc_fn alloc, osqp_free_fn free_fn, void *ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return OSQP_ERR_SETTINGS;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.free = free_fn;
+  g_alloc.ctx = alloc ? ctx : nullptr;
   return OSQP_OK;
 }
 
@@ -1382,8 +1484,8 @@ int update_matrices_impl(osqp_batch *b, int i, const double *P, int P_nnz, const
   }
   // rescale this QP from its raw data (a one-QP list), factor stale
   if (!b->d_subset) {
-    if (hipMalloc(&b->d_subset, sizeof(int) * b->nq) != hipSuccess ||
-        hipMalloc(&b->d_subset_polish, sizeof(int) * b->nq) != hipSuccess)
+    if (dev_alloc(b->alloc, &b->d_subset, sizeof(int) * b->nq) != hipSuccess ||
+        dev_alloc(b->alloc, &b->d_subset_polish, sizeof(int) * b->nq) != hipSuccess)
       return OSQP_ERR_ALLOC;
   }
   b->subset_h.assign(1, i);

@@ -18,9 +18,12 @@ struct QPDesc {
   int lm, ln;                // lanes per row for passes over A rows / over P+A' rows
   int dense;                 // exact PCG preconditioner of P + sigma I + A'RA:
                              // 0 none (Jacobi), 1 dense Cholesky factor,
-                             // 2 diagonal plus low rank (P diagonal; Woodbury)
-  int dld;                   // leading dimension of the dense factor / of S
-  int64_t dense_off;         // offset in the dense arena (1) or low-rank arena (2)
+                             // 2 diagonal plus low rank (P diagonal; Woodbury),
+                             // 3 block-tridiagonal factor after a bandwidth-
+                             //   reducing ordering (band)
+  int dld;                   // leading dimension of the dense factor / of S;
+                             // the block size nb of the band factor
+  int64_t dense_off;         // offset in the dense arena (1, 3) or low-rank arena (2)
   int64_t mr_off;            // offset of the list of A rows with >= 2 entries
   int mr_cnt;                // length of that list
   int plr;                   // 1: polish through the low-rank (Woodbury) condensed solve
@@ -43,6 +46,40 @@ __host__ __device__ inline LRLayout lr_layout(int n, int m, int R, int ldS) {
   L.total = L.wr + m8;
   return L;
 }
+
+// Band block of one QP (dense == 3, doubles, in the low-rank arena): block
+// rows i = 0 .. ceil(n / nb) - 1 of the factor, each two nb x nb row-major
+// tiles, Linv_i = L_ii^-1 (lower) at 2 i nb^2 and C_i = B_i L_ii^-T (upper
+// triangular; zero for the last block row) at (2 i + 1) nb^2; then the FP64
+// residual r (n, variable order) the direct step solves with.
+struct BandLayout {
+  int64_t tiles, r, total;
+};
+__host__ __device__ inline BandLayout band_layout(int n, int nb) {
+  BandLayout L;
+  L.tiles = 0;
+  L.r = 2 * (int64_t)((n + nb - 1) / nb) * nb * nb;
+  L.total = L.r + ((n + 7) & ~7);
+  return L;
+}
+// Per-workgroup scratch (doubles) while a band factor is formed: kBandCopies
+// copies of a block row's strip of K (nb x 2 nb: the sub-diagonal block
+// beside the diagonal block), then D (nb x nb), Bp (nb x nb) and a 64 x 64
+// tile for the inverse of the diagonal factor.
+constexpr int kBandCopies = 4;
+struct BandScratch {
+  int64_t strip, D, Bp, X, total;
+};
+__host__ __device__ inline BandScratch band_scratch_layout(int nb) {
+  BandScratch s;
+  s.strip = 0;
+  s.D = (int64_t)kBandCopies * 2 * nb * nb;
+  s.Bp = s.D + (int64_t)nb * nb;
+  s.X = s.Bp + (int64_t)nb * nb;
+  s.total = s.X + 64 * 64;
+  return s;
+}
+__host__ __device__ inline int64_t band_scratch(int nb) { return band_scratch_layout(nb).total; }
 
 // Per-QP mutable state (device).
 struct QPState {
@@ -105,6 +142,8 @@ struct Batch {
   double *lws;
   long long lws_stride;
   const int *mrows;
+  // band path: position -> variable and variable -> position, n-vector layout
+  const int *bperm, *biperm;
   DevSettings set;
 };
 

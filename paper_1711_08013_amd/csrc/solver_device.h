@@ -34,11 +34,13 @@ struct QPView {
   const double *xws, *yws;
   double *xo, *yo, *zo;
   QPState *st;
-  T *L;              // dense factor (row-major, lower), when dense
+  T *L;              // dense factor (row-major, lower), when dense == 1
   T *Linv;           // inverses of its 64 x 64 diagonal blocks (after L)
-  double *lr;        // low-rank block (lr_layout), when dense == 2
+  double *lr;        // low-rank block (lr_layout), when dense == 2; the band
+                     // block (band_layout), when dense == 3
   int ld, dense, mr_cnt;
   const int *mrows;
+  const int *bperm, *biperm;   // band ordering: position -> variable, inverse
 
   __device__ __forceinline__ QPView(const Batch<T> &b, int k) {
     const QPDesc &ds = b.desc[k];
@@ -66,8 +68,9 @@ struct QPView {
     dense = ds.dense; ld = ds.dld; mr_cnt = ds.mr_cnt;
     L = ds.dense == 1 ? b.dmat + ds.dense_off : nullptr;
     Linv = ds.dense == 1 ? L + (size_t)ds.n * ds.dld : nullptr;
-    lr = ds.dense == 2 ? b.lmat + ds.dense_off : nullptr;
+    lr = (ds.dense == 2 || ds.dense == 3) ? b.lmat + ds.dense_off : nullptr;
     mrows = b.mrows + ds.mr_off;
+    bperm = b.bperm + ds.xo; biperm = b.biperm + ds.xo;
   }
 };
 
@@ -634,6 +637,177 @@ __device__ __forceinline__ void precondition_dense(const WGTeam &tm, const QPVie
 }
 
 // ------------------------------------------------------------------------
+// Band path (dense == 3).  With the ordering found on the host (bperm:
+// position -> variable), the permuted reduced matrix
+//     Kp = (P + sigma I + A'RA)[bperm, bperm]
+// has half-bandwidth at most nb, so in nb x nb blocks it is block
+// tridiagonal: diagonal blocks A_i and sub-diagonal blocks B_i (rows of
+// block i+1, columns of block i).  Its Cholesky factor is block bidiagonal:
+// with D_0 = A_0,
+//     L_ii L_ii' = D_i,   C_i = B_i L_ii^-T,   D_{i+1} = A_{i+1} - C_i C_i',
+// and C_i is upper triangular (B_i is, since the band ends within nb of the
+// diagonal, and L_ii^-T is).  Stored per block row, in FP64: Linv_i = L_ii^-1
+// and C_i.  A solve is a forward sweep y_i = Linv_i (z_i - C_{i-1} y_{i-1})
+// and a backward sweep x_i = Linv_i' (y_i - C_i' x_{i+1}): O(n nb) work and
+// bytes instead of the dense factor's O(n^2).  This is the direct method of
+// Section 3.1 on the reduced system: the symbolic step (the fill-limiting
+// ordering) on the host, the numeric step per QP here, redone on a rho-bar
+// change, and every ADMM step takes x~ += Kp^-1 r in FP64 (the matrix values
+// are the working-precision copies the other passes use, so the factor is
+// exact for the same K).
+// ------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ bool band_form_and_factor(const WGTeam &tm, const QPView<T> &v,
+                                                     DenseLDS<double> &s, double *W,
+                                                     double sigma, double rho_bar) {
+  const int n = v.n, nb = v.ld, nblk = (n + nb - 1) / nb, nb2 = nb * nb;
+  const BandLayout bl = band_layout(n, nb);
+  const BandScratch ws = band_scratch_layout(nb);
+  double *F = v.lr + bl.tiles;
+  double *D = W + ws.D, *Bp = W + ws.Bp, *X = W + ws.X;
+  const int sw = 2 * nb;   // strip row length: columns i0 - nb .. i0 + nb - 1
+  for (int i = 0; i < nblk; ++i) {
+    const int i0 = i * nb, ni = min(nb, n - i0), qlo = i0 - nb;
+    // (1) strip of rows i0 .. i0 + ni - 1, columns qlo .. row (the lower part
+    //     of the band): kBandCopies lanes per row, lane c accumulating every
+    //     c-th term into its own copy (fixed order, no atomics)
+    for (int e = tm.tid; e < kBandCopies * nb * sw; e += tm.nt) W[ws.strip + e] = 0.0;
+    tm.sync();
+    for (int t = tm.tid; t < nb * kBandCopies; t += tm.nt) {
+      const int a = t / kBandCopies, c = t % kBandCopies;
+      if (a >= ni) continue;
+      const int p = i0 + a, j = v.bperm[p];
+      double *row = W + ws.strip + (size_t)c * nb * sw + (size_t)a * sw;
+      for (int k = v.prp[j] + c; k < v.prp[j + 1]; k += kBandCopies) {
+        const int q = v.biperm[v.pci[k]];
+        if (q >= qlo && q <= p) row[q - qlo] += double(v.pv[k]);
+      }
+      if (c == 0) row[p - qlo] += sigma;
+      for (int k = v.atrp[j] + c; k < v.atrp[j + 1]; k += kBandCopies) {
+        const int r = v.atci[k];
+        const double w = (v.iseq[r] ? 1e3 * rho_bar : rho_bar) * double(v.atv[k]);
+        for (int e = v.arp[r]; e < v.arp[r + 1]; ++e) {
+          const int q = v.biperm[v.aci[e]];
+          if (q >= qlo && q <= p) row[q - qlo] += w * double(v.av[e]);
+        }
+      }
+    }
+    tm.sync();
+    for (int e = tm.tid; e < nb * sw; e += tm.nt) {
+      const int a = e / sw, col = e % sw;
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < kBandCopies; ++c) sum += W[ws.strip + (size_t)c * nb * sw + e];
+      if (col >= nb) D[a * nb + (col - nb)] = (a < ni && col - nb <= a) ? sum : 0.0;
+      else Bp[a * nb + col] = a < ni ? sum : 0.0;
+    }
+    tm.sync();
+    if (i > 0) {
+      // (2) C_{i-1} = Bp Linv_{i-1}': C[a][d] = sum_{e <= d} Bp[a][e] Linv[d][e]
+      const double *Lp = F + (size_t)(2 * (i - 1)) * nb2;
+      double *Cp = F + (size_t)(2 * (i - 1) + 1) * nb2;
+      for (int t = tm.tid; t < nb2; t += tm.nt) {
+        const int a = t / nb, d = t % nb;
+        double acc = 0.0;
+        for (int e = 0; e <= d; ++e) acc += Bp[a * nb + e] * Lp[d * nb + e];
+        Cp[t] = a < ni ? acc : 0.0;
+      }
+      tm.sync();
+      // (3) D -= C C' (lower triangle)
+      for (int t = tm.tid; t < nb2; t += tm.nt) {
+        const int a = t / nb, c = t % nb;
+        if (a >= ni || c > a) continue;
+        double acc = 0.0;
+        for (int e = 0; e < nb; ++e) acc += Cp[a * nb + e] * Cp[c * nb + e];
+        D[t] -= acc;
+      }
+      tm.sync();
+    }
+    // (4) D = L_ii L_ii', then Linv_i = L_ii^-1 (the 64 x 64 inverse tile in X)
+    if (!dense_cholesky<double>(tm, s, D, nb, ni)) return false;
+    dense_invert_diag<double>(tm, s, D, nb, ni, X);
+    double *Li = F + (size_t)(2 * i) * nb2;
+    for (int t = tm.tid; t < nb2; t += tm.nt) {
+      const int a = t / nb, c = t % nb;
+      Li[t] = (a < ni && c < ni) ? X[a * 64 + c] : 0.0;
+    }
+    tm.sync();
+  }
+  return true;
+}
+
+// The direct step with the band factor: x~ += Kbar^-1 r, r the FP64
+// residual the start pass left in the band block (variable order).  z (LDS,
+// n doubles) takes r[bperm]; the two sweeps run in place on it; tmp (LDS, 64
+// doubles) holds a block's intermediate vector.  Four lanes per row (or
+// column) of a tile, each over 16 columns (rows), only the tile's nonzero
+// triangle read.
+template <class T>
+__device__ __forceinline__ void band_direct_step(const WGTeam &tm, const QPView<T> &v, double *z,
+                                                 double *tmp) {
+  const int n = v.n, nb = v.ld, nblk = (n + nb - 1) / nb, nb2 = nb * nb;
+  const BandLayout bl = band_layout(n, nb);
+  const double *F = v.lr + bl.tiles, *rv = v.lr + bl.r;
+  tm.sync();
+  for (int p = tm.tid; p < n; p += tm.nt) z[p] = rv[v.bperm[p]];
+  tm.sync();
+  // forward: y_i = Linv_i (z_i - C_{i-1} y_{i-1})
+  for (int i = 0; i < nblk; ++i) {
+    const int i0 = i * nb, ni = min(nb, n - i0);
+    const double *Li = F + (size_t)(2 * i) * nb2;
+    const double *Cp = i > 0 ? F + (size_t)(2 * (i - 1) + 1) * nb2 : nullptr;
+    for (int t = tm.tid; t < nb * 4; t += tm.nt) {
+      const int a = t >> 2, part = t & 3;
+      double acc = 0.0;
+      if (Cp != nullptr && a < ni)
+        for (int d = max(a, part * 16); d < min(nb, part * 16 + 16); ++d)
+          acc += Cp[a * nb + d] * z[i0 - nb + d];
+      acc = group_sum(acc, 4);
+      if (part == 0 && a < ni) tmp[a] = z[i0 + a] - acc;
+    }
+    tm.sync();
+    for (int t = tm.tid; t < nb * 4; t += tm.nt) {
+      const int a = t >> 2, part = t & 3;
+      double acc = 0.0;
+      if (a < ni)
+        for (int e = part * 16; e < min(a + 1, part * 16 + 16); ++e) acc += Li[a * nb + e] * tmp[e];
+      acc = group_sum(acc, 4);
+      if (part == 0 && a < ni) z[i0 + a] = acc;
+    }
+    tm.sync();
+  }
+  // backward: x_i = Linv_i' (y_i - C_i' x_{i+1})
+  for (int i = nblk - 1; i >= 0; --i) {
+    const int i0 = i * nb, ni = min(nb, n - i0);
+    const double *Li = F + (size_t)(2 * i) * nb2;
+    const bool has_next = i + 1 < nblk;
+    const double *Ci = has_next ? F + (size_t)(2 * i + 1) * nb2 : nullptr;
+    const int n1 = has_next ? min(nb, n - i0 - nb) : 0;
+    for (int t = tm.tid; t < nb * 4; t += tm.nt) {
+      const int d = t >> 2, part = t & 3;
+      double acc = 0.0;
+      if (has_next && d < ni)
+        for (int a = part * 16; a < min(min(d + 1, n1), part * 16 + 16); ++a)
+          acc += Ci[a * nb + d] * z[i0 + nb + a];
+      acc = group_sum(acc, 4);
+      if (part == 0 && d < ni) tmp[d] = z[i0 + d] - acc;
+    }
+    tm.sync();
+    for (int t = tm.tid; t < nb * 4; t += tm.nt) {
+      const int d = t >> 2, part = t & 3;
+      double acc = 0.0;
+      if (d < ni)
+        for (int a = max(d, part * 16); a < min(ni, part * 16 + 16); ++a) acc += Li[a * nb + d] * tmp[a];
+      acc = group_sum(acc, 4);
+      if (part == 0 && d < ni) z[i0 + d] = acc;
+    }
+    tm.sync();
+  }
+  for (int p = tm.tid; p < n; p += tm.nt) v.xt[v.bperm[p]] += z[p];
+  tm.sync();
+}
+
+// ------------------------------------------------------------------------
 // Diagonal-plus-low-rank path (P diagonal).  With the rows of A split into
 // single-entry rows and the R multi-entry rows A_m,
 //     K = P + sigma I + A'RA = Delta + B'B,   B = R_m^1/2 A_m  (R x n),
@@ -779,10 +953,13 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   set_rho_and_precond(tm, v, rho_bar, set.sigma);
   // exact preconditioner of K (dense factor, or the low-rank Woodbury form):
   // the stored factor is reused while rho-bar is unchanged
-  const int pre_kind = (v.dense == 1 && dense_ok) ? 1 : ((v.dense == 2 && lr_ok) ? 2 : 0);
+  const int pre_kind = (v.dense == 1 && dense_ok) ? 1
+                     : (v.dense == 2 && lr_ok) ? 2
+                     : (v.dense == 3 && lr_ok) ? 3 : 0;
   auto refactor = [&]() __attribute__((always_inline)) -> bool {
     if constexpr (std::is_same<Team, WGTeam>::value) {
       if (pre_kind == 1) return form_and_factor<T>(tm, v, *dl, dB, set.sigma);
+      if (pre_kind == 3) return band_form_and_factor<T>(tm, v, *dl64, G, set.sigma, rho_bar);
       return lowrank_form_and_factor<T>(tm, v, *dl64, G, set.sigma, rho_bar);
     } else {
       return false;
@@ -849,7 +1026,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   const double floor_rel = sizeof(T) == 4 ? 1e-6 : 1e-12;
   auto pcg_tol = [&](double b0) -> double {
     return have_check ? fmax(set.pcg_tol_frac * fmin(prs, drs), floor_rel * fmax(dnorm, 1e-30))
-                      : 1e-3 * b0;
+                      : 1e-2 * set.pcg_tol_frac * b0;
   };
   // LDS staging of the vectors a pass gathers from (workgroup team): the
   // gathers then hit LDS and only the streamed matrix comes from memory
@@ -859,13 +1036,16 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   const bool stg_kp = stage != nullptr && (int64_t)(n8 + m8) * (int64_t)sizeof(T) <= 8LL * kStage;
   T *stT = reinterpret_cast<T *>(stage);
 
-  // the low-rank form solves K exactly in FP64: there the step is the direct
-  // one (Section 3.1 with the reduced matrix), x~ += K^-1 r, and no PCG runs
-  const int64_t lr_u = pre_kind == 2 ? lr_layout(n, m, v.mr_cnt, v.ld).u : 0;
+  // the low-rank form and the band factor solve K exactly in FP64: there the
+  // step is the direct one (Section 3.1 with the reduced matrix),
+  // x~ += K^-1 r, and no PCG runs.  The start pass leaves in the factor's
+  // block u = Delta^-1 r (low-rank form) or r itself (band factor), in FP64.
+  const int64_t lr_u = pre_kind == 2 ? lr_layout(n, m, v.mr_cnt, v.ld).u
+                     : pre_kind == 3 ? band_layout(n, v.ld).r : 0;
 
   ph = wall_clock64();
   while (true) {
-    const bool direct = pre_kind == 2 && use_dense;
+    const bool direct = (pre_kind == 2 || pre_kind == 3) && use_dense;
     // --- PCG start: r = b - K xt with b = sigma x - q + A'(rho z - y)
     //     (Section 3.1, indirect method), K = P + sigma I + A' R A, using
     //     A xt = zt:  r = sigma (x - xt) - q - P xt + A' s
@@ -884,7 +1064,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
           const double r64 = set.sigma * (xj - xtj) - qj + a;
           const T rj = T(r64);
           v.r[j] = rj;
-          if (direct) v.lr[lr_u + j] = v.lr[j] * r64;   // u = Delta^-1 r in FP64
+          if (direct) v.lr[lr_u + j] = pre_kind == 2 ? v.lr[j] * r64 : r64;
           red[1] = fmax(red[1], fabs(r64));
           if (!use_dense) {
             const T dj = v.minv[j] * rj;
@@ -913,7 +1093,8 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         // inner tolerance ends at another eps-solution than the direct method
         dense_skip = false;
         if (direct) {
-          if (!dense_skip) precondition_lowrank(tm, v, rho_bar, stage, true, true);
+          if (pre_kind == 3) band_direct_step(tm, v, stage, dl64->ys);
+          else precondition_lowrank(tm, v, rho_bar, stage, true, true);
         } else if (!dense_skip) {
           apply_pre();
           for (int j = tm.tid; j < n; j += tm.nt) {
@@ -932,13 +1113,13 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     double rz = red[0], rinf = red[1];
     if (bnorm < 0.0) bnorm = rinf;
     // inner tolerance (reading): kappa * min(prim, dual residual) of the last
-    // check, floored relative to the dual normaliser; 1e-3 of the first
-    // residual before the first check
+    // check, floored relative to the dual normaliser; 1e-2 kappa of the
+    // first residual before the first check (kappa = pcg_tol_frac)
     const double tol = pcg_tol(bnorm);
     int it = (direct && !dense_skip) ? 1 : 0;
     // with the exact factor the first step is taken even below the inner
     // tolerance (unless the residual is exactly zero)
-    const bool forced0 = use_dense && !(rinf > tol);
+    const bool forced0 = !(rinf > tol);
     while (!direct && !dense_skip && (rinf > tol || (forced0 && it == 0 && rinf > 0.0)) &&
            it < set.pcg_max_iter) {
       // t = R A p ; w = P p + sigma p + A' t ; p'w
@@ -973,9 +1154,12 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       tm.template reduce<1, 0>(red);
       const double pw = red[0];
       if (!(pw > 0.0) || !isfinite(pw)) {
-        // a step below the inner tolerance whose curvature underflows is
-        // negligible: x~ stays (not a breakdown)
-        if (!(forced0 && it == 0) || !isfinite(pw)) bad |= 1;
+        // K is positive definite, so a curvature that is not positive comes
+        // from rounding once the residual is small: after the first step, or
+        // on a forced first step below the inner tolerance, x~ stays and the
+        // inner solve ends; a non-positive curvature on a first step above
+        // the tolerance, or a non-finite one, is a breakdown
+        if ((it == 0 && !forced0) || !isfinite(pw)) bad |= 1;
         break;
       }
       const double a_d = rz / pw;

@@ -74,6 +74,11 @@ def test_path_bytes_hand_count():
     work = pcg * (e * (am + a) + 8 * (R * R + 4 * n + 2 * m))
     fact = (1 + rho_up) * (8 * (2 * R * n + R * R) + e * am)
     assert bench.path_bytes([qp], [info]) == admm + work + chk + fact
+    # band direct step: one sweep pair over the FP64 tiles per counted step
+    info["linsys"] = 4
+    work = pcg * (16 * 64 * n + 24 * n)
+    fact = (1 + rho_up) * (16 * 64 * n + e * (a + p))
+    assert bench.path_bytes([qp], [info]) == admm + work + chk + fact
 
 
 def test_stored_traffic_needs_matching_sources_and_shape(monkeypatch, tmp_path):

@@ -147,3 +147,15 @@ def test_binding_canonicalises_csr_input(pm):
                       shape=(2, 2))
     k = pm._Keep(QP(P, np.zeros(2), sp.csr_matrix(np.eye(2)), -np.ones(2), np.ones(2)))
     assert k.Pi.tolist() == [0, 1, 1] and k.Px.tolist() == [0.5, 1.0, 2.0]
+
+
+def test_set_allocator_pairs(pm):
+    """osqp_set_allocator needs both callbacks or neither (no device call)."""
+    L = pm.lib()
+    alloc = pm._ALLOC_FN(lambda n, c: None)
+    assert L.osqp_set_allocator(alloc, pm._FREE_FN(), None) == 6
+    assert L.osqp_set_allocator(pm._ALLOC_FN(), pm._FREE_FN(lambda p, c: None), None) == 6
+    assert L.osqp_set_allocator(pm._ALLOC_FN(), pm._FREE_FN(), None) == 0
+    with pytest.raises(ValueError):
+        pm.set_allocator(lambda n: 0, None)
+    pm.set_allocator()

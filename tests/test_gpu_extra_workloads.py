@@ -1,11 +1,9 @@
 """The remaining appendix problem classes on the GPU through the C ABI --
 equality-constrained QPs, Huber fitting and support vector machines -- at
-the default settings, each against the oracle: status and eps-scaled
-residuals for every instance, and the objective where the reduced system is
-solved exactly (dense factor or low-rank form).  The larger Huber instances
-(n > 2500, and their x columns keep them out of the low-rank form) take the
-Jacobi-preconditioned path, whose inexact inner solves stop at another
-eps-solution; as in the other parity tests those are held to the eps test."""
+the default settings, each against the oracle: status, eps-scaled residuals
+and objective for every instance.  The larger Huber instances (n > 2500,
+and their x columns keep them out of the low-rank form) take the
+Jacobi-preconditioned path."""
 from __future__ import annotations
 
 import pytest
@@ -43,4 +41,4 @@ def test_extra_workloads_match_oracle(pm, precision):
     exact = [row for row, r in zip(rows, res) if r[2]["linsys"] in (2, 3)]
     print(f"  exact-factor paths: {len(exact)} of {len(rows)}", flush=True)
     assert len(exact) >= 10
-    gc.assert_obj_parity(exact, f"extra workloads {precision} (exact paths)")
+    gc.assert_obj_parity(rows, f"extra workloads {precision}")

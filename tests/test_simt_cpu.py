@@ -35,9 +35,9 @@ simt_build = _load_builder()
 
 # the runner's cases, split over four processes that run side by side
 GROUPS = [["shapes"], ["grid"], ["graph", "paths", "mpc"],
-          ["polish", "edges", "certificates", "appendix", "updates", "server"]]
-EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 6, "mpc": 1, "polish": 4, "edges": 6,
-               "certificates": 2, "appendix": 6, "updates": 1, "server": 1}
+          ["polish", "edges", "certificates", "appendix", "updates", "server", "allocator"]]
+EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 8, "mpc": 1, "polish": 4, "edges": 6,
+               "certificates": 2, "appendix": 6, "updates": 1, "server": 1, "allocator": 1}
 
 
 @pytest.fixture(scope="module")
