@@ -306,7 +306,9 @@ void osqp_batch_cleanup(osqp_batch *b);
  * while the device is full, requests accumulate and are admitted together
  * when a launch drains.  Fresh QPs admitted together form a micro-batch set
  * up and solved on its own stream, so launches admitted while others run
- * overlap on the device.  A nonzero structure_key marks QPs that share
+ * overlap on the device; a fresh QP with at least 200,000 matrix entries
+ * (2 nnz(A) + nnz(P) + n + m) gets a launch of its own, so that the small
+ * ones admitted with it do not wait for it.  A nonzero structure_key marks QPs that share
  * matrices: first requests of new keys form a resident pool (matrices,
  * scaling, factors, iterates stay on the device) and later requests of those
  * keys are re-solved together as a subset of their pool through the vector

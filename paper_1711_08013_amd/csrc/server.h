@@ -8,7 +8,9 @@
 // new structure keys one new resident pool, and requests for keys already
 // resident one subset re-solve per pool through the vector update and warm
 // start of Section 6 -- each launched asynchronously on its batch's stream,
-// so work admitted now overlaps work already on the device.
+// so work admitted now overlaps work already on the device.  A large fresh
+// QP gets a launch of its own, so that small ones admitted with it do not
+// wait for it.
 #pragma once
 
 #include <atomic>
@@ -22,6 +24,11 @@
 namespace {
 
 constexpr int kServerMaxLaunches = 8;   // launches on the device at once
+// a fresh QP whose matrices hold at least this many entries (2 nnz(A) +
+// nnz(P full) + n + m, the work queue's cost measure) is launched alone: a
+// launch's results come back when all of its QPs are done, so small QPs
+// admitted in the same round would otherwise wait for it
+constexpr int64_t kServerAloneCost = 200000;
 
 struct OwnedQP {
   int n = 0, m = 0;
@@ -61,6 +68,7 @@ struct ServerReq {
   uint64_t ticket = 0, key = 0;
   OwnedQP qp;
   size_t bytes = 0;
+  int64_t cost = 0;   // 2 nnz(A) + nnz(P full) + n + m
   double t_submit = 0.0;
 };
 
@@ -253,9 +261,9 @@ void server_loop(osqp_server *sv) {
     // ones queued on the device's few hardware queues).  Each round forms
     // one micro-batch of fresh QPs, one new pool of first requests of new
     // keys, and one subset re-solve per resident pool with requests.
-    std::vector<std::shared_ptr<ServerReq>> fresh, firsts;
+    std::vector<std::shared_ptr<ServerReq>> fresh, firsts, alone;
     std::unordered_map<int, std::vector<std::pair<std::shared_ptr<ServerReq>, int>>> repeats;
-    size_t fresh_bytes = 0, first_bytes = 0;
+    size_t fresh_bytes = 0, first_bytes = 0, alone_bytes = 0;
     int new_pool = 0;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
@@ -268,12 +276,23 @@ void server_loop(osqp_server *sv) {
       std::unordered_map<uint64_t, int> chosen;
       for (auto it = sv->queue.begin(); it != sv->queue.end();) {
         auto &rq = *it;
-        int admitted = (int)(fresh.size() + firsts.size());
+        int admitted = (int)(fresh.size() + firsts.size() + alone.size());
         for (auto &kv : repeats) admitted += (int)kv.second.size();
         if (sv->slots + admitted >= sv->max_slots) break;
+        const size_t taken = fresh_bytes + first_bytes + alone_bytes;
+        if (rq->key == 0 && rq->cost >= kServerAloneCost) {
+          // a large fresh QP: a launch of its own (FIFO for fresh QPs)
+          if (launches >= kServerMaxLaunches) break;
+          if (!server_make_room(sv, taken + rq->bytes)) break;
+          ++launches;
+          alone_bytes += rq->bytes;
+          alone.push_back(rq);
+          it = sv->queue.erase(it);
+          continue;
+        }
         if (rq->key == 0) {
           if (fresh.empty() && launches >= kServerMaxLaunches) break;   // FIFO for fresh QPs
-          if (!server_make_room(sv, fresh_bytes + first_bytes + rq->bytes)) break;
+          if (!server_make_room(sv, taken + rq->bytes)) break;
           if (fresh.empty()) ++launches;
           fresh_bytes += rq->bytes;
           fresh.push_back(rq);
@@ -294,7 +313,7 @@ void server_loop(osqp_server *sv) {
         }
         // first request of a key: joins this round's new pool
         if (firsts.empty() && launches >= kServerMaxLaunches) { ++it; continue; }
-        if (!server_make_room(sv, fresh_bytes + first_bytes + rq->bytes)) { ++it; continue; }
+        if (!server_make_room(sv, taken + rq->bytes)) { ++it; continue; }
         if (firsts.empty()) ++launches;
         first_bytes += rq->bytes;
         firsts.push_back(rq);
@@ -306,13 +325,26 @@ void server_loop(osqp_server *sv) {
         new_pool = sv->next_pool++;
         for (auto &r : firsts) sv->pending_keys[r->key] = new_pool;
       }
-      sv->used += fresh_bytes + first_bytes;
-      int admitted = (int)(fresh.size() + firsts.size());
+      sv->used += fresh_bytes + first_bytes + alone_bytes;
+      int admitted = (int)(fresh.size() + firsts.size() + alone.size());
       for (auto &kv : repeats) admitted += (int)kv.second.size();
       sv->slots += admitted;
       sv->peak_bytes = std::max<int64_t>(sv->peak_bytes, (int64_t)sv->used);
     }
     std::vector<InFlight> launched;
+    for (auto &rq : alone) {
+      std::vector<std::shared_ptr<ServerReq>> one{rq};
+      osqp_batch *b = nullptr;
+      const int rc = server_new_batch(sv, one, &b);
+      if (rc == OSQP_OK) {
+        InFlight f;
+        f.b = b; f.kind = 0; f.bytes = rq->bytes; f.reqs = one;
+        f.idx.push_back(0);
+        launched.push_back(std::move(f));
+      } else {
+        server_fail(sv, one, rc, rq->bytes);
+      }
+    }
     if (!fresh.empty()) {
       osqp_batch *b = nullptr;
       const int rc = server_new_batch(sv, fresh, &b);
@@ -422,6 +454,7 @@ osqp_int osqp_server_submit(osqp_server *sv, const osqp_problem *p, uint64_t str
     rq->qp.copy_from(*p, x_ws, y_ws);
     rq->key = structure_key;
     rq->bytes = estimate_bytes(*p, sv->set);
+    rq->cost = 2 * (int64_t)p->A.nnz + 2 * (int64_t)p->P_upper.nnz + p->n + p->m;
     if (rq->bytes > sv->budget) return OSQP_ERR_BUDGET;
     rq->t_submit = now_s();
     std::lock_guard<std::mutex> g(sv->mu);

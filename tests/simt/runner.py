@@ -185,6 +185,8 @@ def case_server():
     rng = qpgen.rng_for(4, 901)
     F, Dd, mu = qpgen.portfolio_model(rng, 100)
     reqs = [(qpgen.random_qp(8, qpgen.rng_for(9, 30 + i)), 0) for i in range(3)]
+    # a fresh QP above the server's size threshold (a launch of its own)
+    reqs.append((qpgen.portfolio(qpgen.rng_for(4, 902), n=1500), 0))
     for _ in range(3):
         mu = 0.8 * mu + 0.2 * rng.standard_normal(mu.size)
         reqs.append((qpgen.portfolio(rng, model=(F, Dd, mu)), 7))
