@@ -292,11 +292,13 @@ osqp_int osqp_batch_get(const osqp_batch *b, osqp_int i, osqp_float *x, osqp_flo
  * the batch's stream). */
 osqp_int osqp_batch_last_kernel_ms(const osqp_batch *b, double *ms);
 osqp_int osqp_batch_count(const osqp_batch *b, osqp_int *count);
-/* Copy the dense Cholesky factor L of problem i's reduced matrix
- * P + sigma I + A'RA (scaled data, current rho; Section 3.1 indirect form)
- * to L_out as n*n row-major doubles, lower triangle (upper part zero).
- * Returns OSQP_ERR_NOT_SETUP when problem i does not use the dense path or
- * has no valid factor yet.  For checking and diagnostics. */
+/* Copy the factor of problem i's reduced matrix K = P + sigma I + A'RA
+ * (scaled data, current rho; Section 3.1) to L_out as n*n row-major doubles:
+ * on the dense path its Cholesky factor L (lower triangle, upper part zero);
+ * on the band path G = Pi' L with L the block-bidiagonal Cholesky factor of
+ * the reordered matrix Pi K Pi' (rows of L put back in variable order), so
+ * that G G' = K.  Returns OSQP_ERR_NOT_SETUP when problem i uses neither
+ * path or has no valid factor yet.  For checking and diagnostics. */
 osqp_int osqp_batch_get_factor(const osqp_batch *b, osqp_int i, osqp_float *L_out);
 void osqp_batch_cleanup(osqp_batch *b);
 

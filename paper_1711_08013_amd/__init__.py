@@ -366,7 +366,10 @@ class Batch:
         return x, y[:m], _info_dict(info)
 
     def factor(self, i: int):
-        """Dense Cholesky factor L (n x n, lower) of problem i's reduced matrix."""
+        """A factor G (n x n) of problem i's reduced matrix, G G' = K: the
+        dense Cholesky factor (lower) or, on the band path, the block-
+        bidiagonal factor of the reordered matrix with its rows in variable
+        order (osqp_batch_get_factor)."""
         n, _ = self.sizes[self._index(i)]
         L = np.zeros((n, n))
         _check(lib().osqp_batch_get_factor(self._h, i, _ptr(L)), "osqp_batch_get_factor")

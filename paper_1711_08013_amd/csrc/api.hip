@@ -1609,12 +1609,49 @@ osqp_int osqp_batch_get_factor(const osqp_batch *b, osqp_int i, osqp_float *L_ou
   if (!b || !L_out) return OSQP_ERR_NOT_SETUP;
   if (i < 0 || i >= b->nq) return OSQP_ERR_INDEX;
   const QPDesc &d = b->desc[i];
-  if (d.dense != 1) return OSQP_ERR_NOT_SETUP;
+  if (d.dense != 1 && d.dense != 3) return OSQP_ERR_NOT_SETUP;
   QPState st;
   const QPState *dst = b->fp64 ? b->bd.st : b->bf.st;
   if (hipMemcpy(&st, dst + i, sizeof(QPState), hipMemcpyDeviceToHost) != hipSuccess)
     return OSQP_ERR_DEVICE;
   if (st.factor_rho == 0.0) return OSQP_ERR_NOT_SETUP;
+  if (d.dense == 3) {
+    // band factor: L (block bidiagonal, of the permuted matrix) from its
+    // tiles -- L_ii = (Linv_i)^-1 by forward substitution, L_{i+1,i} = C_i --
+    // then its rows put back in variable order: G = P' L, G G' = K
+    const int n = d.n, nb = d.dld, nblk = (n + nb - 1) / nb, nb2 = nb * nb;
+    const BandLayout bl = band_layout(n, nb);
+    std::vector<double> F((size_t)bl.r);
+    const double *lm = b->fp64 ? b->bd.lmat : b->bf.lmat;
+    if (hipMemcpy(F.data(), lm + d.dense_off, F.size() * sizeof(double), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return OSQP_ERR_DEVICE;
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int bk = 0; bk < nblk; ++bk) {
+      const int i0 = bk * nb, ni = std::min(nb, n - i0);
+      const double *Li = F.data() + (size_t)(2 * bk) * nb2;
+      // X = Li^-1 (lower): row r of X solves sum_q Li[r][q] X[q][c] = delta_rc
+      std::vector<double> X((size_t)ni * ni, 0.0);
+      for (int c = 0; c < ni; ++c)
+        for (int r = c; r < ni; ++r) {
+          double v = r == c ? 1.0 : 0.0;
+          for (int q = c; q < r; ++q) v -= Li[r * nb + q] * X[(size_t)q * ni + c];
+          X[(size_t)r * ni + c] = v / Li[r * nb + r];
+        }
+      for (int r = 0; r < ni; ++r)
+        for (int c = 0; c <= r; ++c) L[(size_t)(i0 + r) * n + i0 + c] = X[(size_t)r * ni + c];
+      if (bk + 1 < nblk) {
+        const double *Ci = F.data() + (size_t)(2 * bk + 1) * nb2;
+        const int n1 = std::min(nb, n - i0 - nb);
+        for (int r = 0; r < n1; ++r)
+          for (int c = 0; c < ni; ++c) L[(size_t)(i0 + nb + r) * n + i0 + c] = Ci[r * nb + c];
+      }
+    }
+    const int *perm = b->bperm_h.data() + d.xo;
+    for (int p = 0; p < n; ++p)
+      std::memcpy(L_out + (size_t)perm[p] * n, L.data() + (size_t)p * n, sizeof(double) * n);
+    return OSQP_OK;
+  }
   const size_t cnt = (size_t)d.n * d.dld;
   if (b->fp64) {
     std::vector<double> tmp(cnt);

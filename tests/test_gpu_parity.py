@@ -308,16 +308,22 @@ def test_auto_path_choice(pm):
     assert [r[2]["linsys"] for r in res] == [3, 3, 3, 4, 4, 2, 2]
 
 
+@pytest.mark.parametrize("linsys", ["dense", "band"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_dense_factor_is_cholesky_of_reduced_matrix(pm, precision):
-    """The MFMA-formed, MFMA-factored dense matrix: L L' equals
+def test_factor_is_cholesky_of_reduced_matrix(pm, precision, linsys):
+    """The MFMA-formed, MFMA-factored dense matrix and the band factor (block
+    bidiagonal after the reverse Cuthill-McKee ordering, FP64): L L' equals
     Pbar + sigma I + Abar' R Abar recomputed in numpy from the scaled data
     (scaling from the oracle's independent Ruiz, same passes and readings)."""
-    qps = [qpgen.config_instance(1, 0), qpgen.config_instance(3, 1),
-           qpgen.config_instance(4, 2, n_range=(100, 300))]
-    b = pm.Batch(qps, precision=precision, linsys="dense", max_iter=1, adaptive_rho=0)
+    if linsys == "dense":
+        qps = [qpgen.config_instance(1, 0), qpgen.config_instance(3, 1),
+               qpgen.config_instance(4, 2, n_range=(100, 300))]
+    else:
+        qps = [qpgen.mpc(qpgen.rng_for(3, 70 + i), T=8 + 6 * i) for i in range(3)]
+    b = pm.Batch(qps, precision=precision, linsys=linsys, max_iter=1, adaptive_rho=0)
     b.solve()
     for i, qp in enumerate(qps):
+        assert b.get(i)[2]["linsys"] == LINSYS_CODE[linsys]
         L = b.factor(i)
         D, E, c = oracle.ruiz(qp, 10)
         Pb = c * (D[:, None] * qp.full_P().toarray() * D[None, :])
@@ -325,6 +331,8 @@ def test_dense_factor_is_cholesky_of_reduced_matrix(pm, precision):
         rho = np.where(qp.l == qp.u, 1e3 * 0.1, 0.1)
         K = Pb + 1e-6 * np.eye(qp.n) + Ab.T @ (rho[:, None] * Ab)
         err = np.max(np.abs(L @ L.T - K)) / np.max(np.abs(K))
+        # the band factor is FP64 in both precisions, from the FP32 copies of
+        # the scaled data in the FP32 path
         tol = 2e-5 if precision == "fp32" else 1e-12
         print(f"  {qp.name} {precision}: rel err of L L' {err:.2e}", flush=True)
         assert err <= tol, err
