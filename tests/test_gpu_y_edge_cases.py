@@ -1,8 +1,9 @@
 """Degenerate and edge inputs on the GPU through the C ABI, against closed
 forms and the oracle: a scalar QP, no constraints at all (m = 0), A = I
 (no multi-entry rows, so the dense factor has no rank-k part), a linear
-program (P = 0), and rows of A that are empty or free (infinite bounds on
-both sides), which must not change the solution."""
+program (P = 0), rows of A that are empty or free (infinite bounds on
+both sides), which must not change the solution, and the band factor on
+edge patterns (zero bandwidth, a ragged last block, a chain)."""
 from __future__ import annotations
 
 import numpy as np
@@ -148,3 +149,42 @@ def test_batch_of_degenerate_and_regular_qps(pm):
         xa, ya, ia = pm.solve(qp, precision="fp32")
         assert info["status_name"] == ia["status_name"] == "solved", qp.name
         assert np.array_equal(x, xa) and np.array_equal(y, ya), qp.name
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_band_factor_degenerate_bands(pm, precision):
+    """The band factor on edge patterns: a diagonal P with no constraints
+    (half-bandwidth 0, blocks of 8, a ragged last block) against the closed
+    form x = -q / d; and a chain (tridiagonal P, rows x_i - x_{i+1} with
+    bounds) with an empty row and a free row added, against the oracle and
+    against the chain without those rows."""
+    rng = np.random.default_rng(21)
+    e = EPS[precision]
+    kw = dict(eps_abs=e, eps_rel=e, max_iter=50000)
+    n = 43
+    d = rng.uniform(0.5, 3.0, n)
+    q = rng.standard_normal(n)
+    qp = QP(sp.csr_matrix(np.diag(d)), q, sp.csr_matrix((0, n)), np.zeros(0), np.zeros(0),
+            name="diag m=0")
+    x, y, info = pm.solve(qp, precision=precision, linsys="band", **kw)
+    assert info["linsys"] == 4 and info["status_name"] == "solved"
+    assert np.allclose(x, -q / d, atol=1e-6)
+    # chain
+    n = 150
+    main = rng.uniform(1.0, 2.0, n)
+    off = rng.uniform(-0.4, 0.4, n - 1)
+    P = sp.diags([main, off, off], [0, 1, -1]).toarray()
+    D = sp.diags([np.ones(n - 1), -np.ones(n - 1)], [0, 1], shape=(n - 1, n)).toarray()
+    A = np.vstack([D, np.zeros((1, n)), np.eye(n)[:1]])
+    l = np.concatenate([-0.3 * np.ones(n - 1), [-1.0], [-np.inf]])
+    u = np.concatenate([0.3 * np.ones(n - 1), [1.0], [np.inf]])
+    q = 3.0 * rng.standard_normal(n)
+    base = _qp(P, q, D, -0.3 * np.ones(n - 1), 0.3 * np.ones(n - 1), "chain")
+    ext = _qp(P, q, A, l, u, "chain + empty + free rows")
+    xb, yb, ib = pm.solve(base, precision=precision, **kw)
+    x, y, info = pm.solve(ext, precision=precision, **kw)
+    assert ib["linsys"] == info["linsys"] == 4
+    gc.compare(ext, x, y, info, oracle.solve(ext, **kw), eps_abs=e, eps_rel=e)
+    assert info["status_name"] == ib["status_name"] == "solved"
+    assert abs(info["obj_val"] - ib["obj_val"]) <= 1e-4 * max(1.0, abs(ib["obj_val"]))
+    assert np.allclose(y[n - 1:], 0.0, atol=1e-6)
