@@ -853,9 +853,12 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       }
       if (want) cand.push_back(k);
     }
+    // per-workgroup scratch: one slot per workgroup a launch can have, at
+    // most one per QP (every launch's grid is min(QPs listed, grid_wg))
+    const int slots = std::min(b->grid_wg, count);
     if (b->lr_total > 0) {
       b->lws_stride = (gmax + 63) & ~int64_t(63);
-      b->lws_slots = b->grid_wg;
+      b->lws_slots = slots;
     }
     std::stable_sort(cand.begin(), cand.end(),
                      [&](int a, int c) { return probs[a].n < probs[c].n; });
@@ -877,7 +880,7 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
     }
     if (b->dense_total > 0) {
       b->dws_stride = ((int64_t)nmax * rmax + 63) & ~int64_t(63);
-      b->dws_slots = b->grid_wg;
+      b->dws_slots = slots;
     }
   }
 

@@ -1036,16 +1036,21 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
   const bool stg_kp = stage != nullptr && (int64_t)(n8 + m8) * (int64_t)sizeof(T) <= 8LL * kStage;
   T *stT = reinterpret_cast<T *>(stage);
 
-  // the low-rank form and the band factor solve K exactly in FP64: there the
-  // step is the direct one (Section 3.1 with the reduced matrix),
-  // x~ += K^-1 r, and no PCG runs.  The start pass leaves in the factor's
-  // block u = Delta^-1 r (low-rank form) or r itself (band factor), in FP64.
+  // the low-rank form, the band factor and (FP64 path) the dense factor
+  // solve K exactly in FP64: there the step is the direct one (Section 3.1
+  // with the reduced matrix), x~ += K^-1 r, and no PCG runs.  The start pass
+  // leaves u = Delta^-1 r (low-rank form) or r itself (band factor) in the
+  // factor's block, in FP64; the dense factor solves from r in place.
   const int64_t lr_u = pre_kind == 2 ? lr_layout(n, m, v.mr_cnt, v.ld).u
                      : pre_kind == 3 ? band_layout(n, v.ld).r : 0;
 
   ph = wall_clock64();
   while (true) {
-    const bool direct = (pre_kind == 2 || pre_kind == 3) && use_dense;
+    // the exact factors in FP64 -- low-rank form, band factor, and the
+    // dense factor of the FP64 path -- take the direct step; the FP32 dense
+    // factor preconditions PCG
+    const bool direct =
+        (pre_kind == 2 || pre_kind == 3 || (pre_kind == 1 && sizeof(T) == 8)) && use_dense;
     // --- PCG start: r = b - K xt with b = sigma x - q + A'(rho z - y)
     //     (Section 3.1, indirect method), K = P + sigma I + A' R A, using
     //     A xt = zt:  r = sigma (x - xt) - q - P xt + A' s
@@ -1064,7 +1069,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
           const double r64 = set.sigma * (xj - xtj) - qj + a;
           const T rj = T(r64);
           v.r[j] = rj;
-          if (direct) v.lr[lr_u + j] = pre_kind == 2 ? v.lr[j] * r64 : r64;
+          if (direct && pre_kind != 1) v.lr[lr_u + j] = pre_kind == 2 ? v.lr[j] * r64 : r64;
           red[1] = fmax(red[1], fabs(r64));
           if (!use_dense) {
             const T dj = v.minv[j] * rj;
@@ -1093,8 +1098,16 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
         // inner tolerance ends at another eps-solution than the direct method
         dense_skip = false;
         if (direct) {
-          if (pre_kind == 3) band_direct_step(tm, v, stage, dl64->ys);
-          else precondition_lowrank(tm, v, rho_bar, stage, true, true);
+          if (pre_kind == 3) {
+            band_direct_step(tm, v, stage, dl64->ys);
+          } else if (pre_kind == 1) {
+            // FP64 dense factor: d = K^-1 r, x~ += d
+            apply_pre();
+            for (int j = tm.tid; j < n; j += tm.nt) v.xt[j] += double(v.d[j]);
+            tm.sync();
+          } else {
+            precondition_lowrank(tm, v, rho_bar, stage, true, true);
+          }
         } else if (!dense_skip) {
           apply_pre();
           for (int j = tm.tid; j < n; j += tm.nt) {
