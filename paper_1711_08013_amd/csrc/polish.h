@@ -85,7 +85,11 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
   // active multi-entry rows, in row order: a ballot per wave, the waves'
   // counts in LDS, then each thread's position (deterministic)
   __shared__ int wcount[kMaxPolishWaves];
+  // the reset is ordered before every read of the count, also when the QP
+  // has no multi-entry rows and the loop below never runs (R_sh still holds
+  // the previous QP's count in this workgroup's LDS)
   if (tm.tid == 0) R_sh = 0;
+  tm.sync();
   {
     const int lane = tm.tid & (kWave - 1), wv = tm.tid >> 6, nw = tm.nt >> 6;
     for (int r0 = 0; r0 < v.mr_cnt; r0 += tm.nt) {

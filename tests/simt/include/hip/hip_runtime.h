@@ -368,6 +368,17 @@ inline void run_blocks(const std::vector<int> &bids, int nt, int gdim,
     if (all_done) break;
     if (!ran && !progress) {
       std::fprintf(stderr, "simt: deadlock (%d blocks from %d)\n", nblk, bids[0]);
+      // where the threads wait: runs of equal (state, call site)
+      static const char *names[] = {"run", "barrier", "cross-lane", "done"};
+      for (int t = 0; t < total;) {
+        int e = t + 1;
+        while (e < total && s.f[e].state == s.f[t].state && s.f[e].lane.line == s.f[t].lane.line &&
+               s.f[e].lane.file == s.f[t].lane.file)
+          ++e;
+        std::fprintf(stderr, "  threads %d-%d: %s at %s:%d\n", t, e - 1, names[s.f[t].state],
+                     s.f[t].lane.file ? s.f[t].lane.file : "?", s.f[t].lane.line);
+        t = e;
+      }
       std::abort();
     }
   }
@@ -473,7 +484,11 @@ inline const ::simt::DimRef blockIdx{::simt::g_bid, 0u, 0u};
 inline const ::simt::DimRef blockDim{::simt::g_bdim, 1u, 1u};
 inline const ::simt::DimRef gridDim{::simt::g_gdim, 1u, 1u};
 
-inline void __syncthreads() { ::simt::wait(::simt::BARRIER); }
+inline void __syncthreads(const char *file = __builtin_FILE(), int line = __builtin_LINE()) {
+  ::simt::Lane &L = ::simt::me();
+  L.file = file; L.line = line;
+  ::simt::wait(::simt::BARRIER);
+}
 inline void __threadfence() {}
 
 template <class T>

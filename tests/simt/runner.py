@@ -64,7 +64,7 @@ def case_paths():
             res = pm.solve(qp, precision=prec, linsys=path)
             assert res[2]["linsys"] == code[path], (path, res[2]["linsys"])
             _same_as_oracle(qp, res, exact_iters=(prec == "fp64" and path != "pcg"))
-            if path in ("band", "lowrank"):
+            if path in ("band", "lowrank") or (path == "dense" and prec == "fp64"):
                 assert res[2]["pcg_iter"] == res[2]["iter"], res[2]   # one direct step each
             yield f"{path} {prec} iter {res[2]['iter']}"
 
@@ -87,6 +87,33 @@ def case_polish():
             if res[2]["polish_status"] == 1 and ref.polish_status == 1:
                 assert row["obj_err"] <= 1e-6, (qp.name, row["obj_err"])
             yield f"polish {qp.name} {prec} status {res[2]['polish_status']}"
+
+
+def case_polish_batch():
+    """Forty tiny QPs polished in one batch: a workgroup polishes several QPs
+    in turn, QPs with multi-entry active rows next to QPs without (the
+    count of those rows must not leak from one QP to the next); each
+    accepted polish is the enumerated optimum."""
+    from tests import qpcheck
+    from tests.test_oracle_pins import _tiny_random
+    qps = [_tiny_random(s) for s in range(40)]
+    mixed = {bool(np.any(np.diff(q.A.indptr) > 1)) for q in qps}
+    assert mixed == {True, False}, mixed
+    for prec in ("fp32", "fp64"):
+        b = pm.Batch(qps, precision=prec, polish=1)
+        b.solve()
+        ok = 0
+        for i, qp in enumerate(qps):
+            x, y, info = b.get(i)
+            assert info["status_name"] == "solved", (qp.name, info["status_name"])
+            if info["polish_status"] == 1:
+                ok += 1
+                x_bf, _, f_bf = qpcheck.brute_force(qp)
+                assert np.allclose(x, x_bf, atol=1e-7), qp.name
+                assert abs(info["obj_val"] - f_bf) <= 1e-8 * max(1.0, abs(f_bf)), qp.name
+        b.close()
+        assert ok >= 30, ok
+        yield f"polish batch x40 {prec} accepted {ok}"
 
 
 def case_shapes():
@@ -331,7 +358,8 @@ def case_allocator():
     yield f"allocator: {calls[0]} allocations through the hook, all returned"
 
 
-CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish, "shapes": case_shapes,
+CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish,
+         "polish_batch": case_polish_batch, "shapes": case_shapes,
          "graph": case_graph, "grid": case_grid,
          "server": case_server,
          "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,

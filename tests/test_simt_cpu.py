@@ -3,13 +3,14 @@ host against a stand-in HIP runtime that executes every workgroup thread as
 a fiber with wave-level shuffles, ballots and 16x16x4 matrix products
 emulated (tests/simt), under the host address sanitizer.  The same C ABI
 then solves the cases of tests/simt/runner.py -- every linear-system path
-in both precisions, polishing, every launch shape set_shape accepts
-shapes, graph replays, the whole-grid team of a cooperative launch, the
-serving loop, degenerate inputs, certificates, the appendix
+in both precisions, polishing (single QPs, and a batch in which a
+workgroup polishes QPs of different shapes in turn), every launch shape
+set_shape accepts, graph replays, the whole-grid team of a cooperative
+launch, the serving loop, degenerate inputs, certificates, the appendix
 problem classes and the parametric updates -- and each result is compared
-with the oracle.  A
-device-memory access outside its allocation aborts the run with the
-sanitizer's report.  This checks the kernels' logic and indexing, not the
+with the oracle.  A device-memory access outside its allocation aborts the
+run with the sanitizer's report, and a barrier or cross-lane operation
+that not every thread reaches aborts it with the call sites.  This checks the kernels' logic and indexing, not the
 GPU's timing or its hardware-specific behaviour."""
 from __future__ import annotations
 
@@ -35,8 +36,10 @@ simt_build = _load_builder()
 
 # the runner's cases, split over four processes that run side by side
 GROUPS = [["shapes"], ["grid"], ["graph", "paths", "mpc"],
-          ["polish", "edges", "certificates", "appendix", "updates", "server", "allocator"]]
-EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 8, "mpc": 1, "polish": 4, "edges": 6,
+          ["polish", "polish_batch", "edges", "certificates", "appendix", "updates", "server",
+           "allocator"]]
+EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 8, "mpc": 1, "polish": 4, "polish_batch": 2,
+               "edges": 6,
                "certificates": 2, "appendix": 6, "updates": 1, "server": 1, "allocator": 1}
 
 
@@ -90,4 +93,11 @@ def test_gpu_edge_case_file_on_cpu_kernels(simt_lib):
                        capture_output=True, text=True, env=env, cwd=ROOT, timeout=900)
     print(r.stdout[-3000:])
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
-    assert "11 passed" in r.stdout
+    # every GPU test of the file ran and passed (none skipped)
+    c = subprocess.run([sys.executable, "-m", "pytest", "--collect-only", "-q", "-m", "gpu",
+                        "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_gpu_y_edge_cases.py")],
+                       capture_output=True, text=True, cwd=ROOT, timeout=300)
+    n = sum(1 for line in c.stdout.splitlines() if "::" in line)
+    assert n >= 13, c.stdout
+    assert f"{n} passed" in r.stdout and "skipped" not in r.stdout, r.stdout[-500:]
