@@ -1088,15 +1088,12 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
       start_pass(v.s64, v.xt);
     }
     // the dense preconditioner is a factor of K itself: one PCG step with it
-    // is the exact solve
-    bool dense_skip = false;
+    // is the exact solve.  With an exact factor every ADMM step takes its
+    // linear solve, as the direct method does (skipping it while the residual
+    // is under the inner tolerance ends at another eps-solution)
     if constexpr (std::is_same<Team, WGTeam>::value) {
       if (use_dense) {
         tm.template reduce<0, 1>(red + 1);
-        // with an exact factor every ADMM step takes its linear solve, as the
-        // direct method does: skipping it while the residual is under the
-        // inner tolerance ends at another eps-solution than the direct method
-        dense_skip = false;
         if (direct) {
           if (pre_kind == 3) {
             band_direct_step(tm, v, stage, dl64->ys);
@@ -1108,7 +1105,7 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
           } else {
             precondition_lowrank(tm, v, rho_bar, stage, true, true);
           }
-        } else if (!dense_skip) {
+        } else {
           apply_pre();
           for (int j = tm.tid; j < n; j += tm.nt) {
             const T dj = v.d[j];
@@ -1129,11 +1126,11 @@ __device__ __forceinline__ void solve_qp(const Team &tm, const QPView<T> &v, con
     // check, floored relative to the dual normaliser; 1e-2 kappa of the
     // first residual before the first check (kappa = pcg_tol_frac)
     const double tol = pcg_tol(bnorm);
-    int it = (direct && !dense_skip) ? 1 : 0;
+    int it = direct ? 1 : 0;
     // with the exact factor the first step is taken even below the inner
     // tolerance (unless the residual is exactly zero)
     const bool forced0 = !(rinf > tol);
-    while (!direct && !dense_skip && (rinf > tol || (forced0 && it == 0 && rinf > 0.0)) &&
+    while (!direct && (rinf > tol || (forced0 && it == 0 && rinf > 0.0)) &&
            it < set.pcg_max_iter) {
       // t = R A p ; w = P p + sigma p + A' t ; p'w
       auto kprod = [&](const T *p_src, T *t_dst, const T *t_src) __attribute__((always_inline)) {
