@@ -308,9 +308,14 @@ inline void run_blocks(const std::vector<int> &bids, int nt, int gdim,
   // per-workgroup LDS images when several workgroups run side by side
   const size_t lds_bytes = (__start_simt_lds && __stop_simt_lds)
                                ? size_t(__stop_simt_lds - __start_simt_lds) : 0;
+  // LDS holds junk when a workgroup starts (as on the device, where it
+  // keeps whatever the previous workgroup on that CU left): every byte is
+  // set to 0xFF, a NaN in every float and double and -1 in every integer, so
+  // a read before the workgroup's own write shows in the results
   std::vector<std::vector<char>> lds;
   int lds_loaded = 0;
-  if (nblk > 1 && lds_bytes) lds.assign(nblk, std::vector<char>(__start_simt_lds, __stop_simt_lds));
+  if (lds_bytes) std::memset(__start_simt_lds, 0xFF, lds_bytes);
+  if (nblk > 1 && lds_bytes) lds.assign(nblk, std::vector<char>(lds_bytes, char(0xFF)));
   // sweeps alternate between ascending and descending thread order, so a
   // read that is not ordered after its write by a barrier sees the stale
   // value in one of the two orders
@@ -625,7 +630,7 @@ inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, F fn, int
 }
 inline hipError_t hipMalloc(void **p, size_t bytes) {
   *p = std::malloc(bytes ? bytes : 1);
-  if (*p) std::memset(*p, 0xA5, bytes);   // device memory starts with junk
+  if (*p) std::memset(*p, 0xFF, bytes);   // device memory starts with junk (NaN, -1)
   return *p ? hipSuccess : hipErrorInvalidValue;
 }
 template <class T>
@@ -634,7 +639,7 @@ inline hipError_t hipMalloc(T **p, size_t bytes) { return hipMalloc((void **)p, 
 inline void *simt_array_alloc(size_t bytes) {
   const size_t b = (bytes + 15) & ~size_t(15);
   void *p = std::malloc(b ? b : 16);
-  if (p) std::memset(p, 0xA5, b ? b : 16);
+  if (p) std::memset(p, 0xFF, b ? b : 16);
   return p;
 }
 inline hipError_t hipFree(void *p) { std::free(p); return hipSuccess; }
