@@ -188,3 +188,31 @@ def test_band_factor_degenerate_bands(pm, precision):
     assert info["status_name"] == ib["status_name"] == "solved"
     assert abs(info["obj_val"] - ib["obj_val"]) <= 1e-4 * max(1.0, abs(ib["obj_val"]))
     assert np.allclose(y[n - 1:], 0.0, atol=1e-6)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_failed_factor_falls_back_to_jacobi(pm, precision):
+    """A reduced matrix whose FP32 Cholesky meets a zero pivot: P couples two
+    variables with weight 1e8 and the box rows add rho = 0.1 to its diagonal,
+    which FP32 rounds away (no Ruiz scaling to even it out), so the second
+    pivot is 1e8 - 1e8 = 0.  In FP32 the dense path then solves with Jacobi
+    PCG, step for step as the Jacobi path does; in FP64 the factor holds and
+    each ADMM step is the exact direct step (the oracle's iteration count).
+    Both hold the oracle's status and objective."""
+    a = 1e8
+    P = sp.csr_matrix(np.array([[a, a, 0.0], [0.0, a, 0.0], [0.0, 0.0, 1.0]]))
+    qp = QP(P, np.array([1.0, -1.0, 0.5]), sp.csr_matrix(np.eye(3)), -np.ones(3), np.ones(3),
+            name="coupled 1e8")
+    kw = dict(scaling_iters=0)
+    ref = oracle.solve(qp, **kw)
+    xd, yd, idn = pm.solve(qp, precision=precision, linsys="dense", **kw)
+    xj, yj, ij = pm.solve(qp, precision=precision, linsys="pcg", **kw)
+    assert idn["linsys"] == 2 and ij["linsys"] == 1
+    for x, y, info in ((xd, yd, idn), (xj, yj, ij)):
+        row = gc.compare(qp, x, y, info, ref)
+        gc.assert_obj_parity([row], f"{qp.name} {precision} linsys {info['linsys']}")
+    if precision == "fp32":
+        assert np.array_equal(xd, xj) and np.array_equal(yd, yj)
+        assert (idn["iter"], idn["pcg_iter"]) == (ij["iter"], ij["pcg_iter"])
+    else:
+        assert idn["pcg_iter"] == idn["iter"] == ref.iter
