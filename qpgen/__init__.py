@@ -26,7 +26,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "QP", "rng_for", "sparse_normal", "random_qp", "eq_qp", "lasso",
-    "mpc", "portfolio", "huber", "box_qp", "config_instance", "serving_trace",
+    "mpc", "portfolio", "huber", "banded", "box_qp", "config_instance", "serving_trace",
 ]
 
 
@@ -287,6 +287,30 @@ def huber(rng: np.random.Generator, n_features: int, m_data: int | None = None,
     l = np.concatenate([b, np.zeros(2 * md)])
     u = np.concatenate([b, np.inf * np.ones(2 * md)])
     return QP(_upper(Pfull), q, _csr(A), l, u, name=f"huber(nf={nf},md={md})")
+
+
+# --------------------------------------------------------------------------
+# A banded structure of a chosen half-bandwidth (edge cases of the band factor)
+# --------------------------------------------------------------------------
+def banded(rng: np.random.Generator, n: int, w: int, stride: int = 8) -> QP:
+    """A QP whose reduced matrix P + A'RA has half-bandwidth exactly w in the
+    natural order: P tridiagonal (diagonal U[1, 2], off-diagonal U[-0.3,
+    0.3]), rows of A over the windows of w + 1 consecutive variables starting
+    every `stride`-th variable (entries N(0, 1/(w+1)), bounds [-0.5, 0.5]),
+    then a box [-1, 1] on every variable; q ~ N(0, 4)."""
+    main = rng.uniform(1.0, 2.0, n)
+    off = rng.uniform(-0.3, 0.3, n - 1)
+    P = sp.diags([main, off], [0, 1], format="csr")
+    starts = np.arange(0, n - w, stride)
+    rows = np.repeat(np.arange(len(starts)), w + 1)
+    cols = (starts[:, None] + np.arange(w + 1)[None, :]).ravel()
+    vals = rng.standard_normal(len(cols)) / math.sqrt(w + 1)
+    W = sp.csr_matrix((vals, (rows, cols)), shape=(len(starts), n))
+    A = sp.vstack([W, sp.identity(n)], format="csr")
+    l = np.concatenate([-0.5 * np.ones(len(starts)), -np.ones(n)])
+    u = np.concatenate([0.5 * np.ones(len(starts)), np.ones(n)])
+    q = 2.0 * rng.standard_normal(n)
+    return QP(_csr(P), q, _csr(A), l, u, name=f"banded(n={n},w={w})")
 
 
 # --------------------------------------------------------------------------

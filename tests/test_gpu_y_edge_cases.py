@@ -216,3 +216,21 @@ def test_failed_factor_falls_back_to_jacobi(pm, precision):
         assert (idn["iter"], idn["pcg_iter"]) == (ij["iter"], ij["pcg_iter"])
     else:
         assert idn["pcg_iter"] == idn["iter"] == ref.iter
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_band_factor_at_its_largest(pm, precision):
+    """The band path at its limits: n = 8192 variables (the permuted vector
+    of the direct step fills the LDS stage exactly) and half-bandwidth 64
+    (the largest block), 128 blocks.  The automatic choice takes the band
+    factor; status and objective are the oracle's, and each ADMM step is one
+    direct step (in FP64 with the oracle's iteration count)."""
+    qp = qpgen.banded(np.random.default_rng(5), 8192, 64)
+    ref = oracle.solve(qp)
+    x, y, info = pm.solve(qp, precision=precision)
+    assert info["linsys"] == 4, info["linsys"]
+    row = gc.compare(qp, x, y, info, ref)
+    gc.assert_obj_parity([row], f"{qp.name} {precision}")
+    assert info["pcg_iter"] == info["iter"]
+    if precision == "fp64":
+        assert info["iter"] == ref.iter

@@ -118,3 +118,17 @@ def test_long_row_is_refused(driver):
     qp = qpgen.config_instance(4, 0, n_range=(100, 101))   # the dense row 1'x = 1
     bw, _ = _order(driver, qp, max_row=65)
     assert bw == -1
+
+
+@pytest.mark.parametrize("n,w", [(8192, 64), (8192, 56), (1000, 64)])
+def test_banded_pattern_keeps_its_bandwidth(driver, n, w):
+    """Windows of w + 1 consecutive variables (half-bandwidth w in the
+    natural order): the ordering finds no narrower band and no wider one, so
+    at n = 8192, w = 64 the device factor takes its largest block (64) and
+    the permuted vector fills the solve's LDS stage exactly."""
+    qp = qpgen.banded(np.random.default_rng(5), n, w)
+    bw, perm = _order(driver, qp)
+    assert sorted(perm.tolist()) == list(range(n))
+    assert bw == w == _bandwidth(qp, perm)
+    # the rows hold w + 1 entries: one more than the limit refuses them
+    assert _order(driver, qp, max_row=w)[0] == -1
