@@ -101,3 +101,37 @@ def test_gpu_edge_case_file_on_cpu_kernels(simt_lib):
     n = sum(1 for line in c.stdout.splitlines() if "::" in line)
     assert n >= 13, c.stdout
     assert f"{n} passed" in r.stdout and "skipped" not in r.stdout, r.stdout[-500:]
+
+
+# Every GPU test file against the emulated kernels: an hour or more per file,
+# so only on request (OSQPMI_EMULATE_GPU_FILES=1).  The cases sized for the
+# device alone (the full-size Lasso, the benchmark's full batches) are left
+# out; the batched file runs on three emulated CUs, where its whole-grid
+# launch is 1,536 fibers instead of 131,072.
+GPU_FILES = [
+    ("test_gpu_parity.py", "not lasso_full_size", None),
+    ("test_gpu_batched.py", None, "3"),
+    ("test_gpu_parametric.py", None, None),
+    ("test_gpu_high_accuracy.py", None, None),
+    ("test_gpu_serving.py", None, None),
+    ("test_gpu_extra_workloads.py", None, None),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("OSQPMI_EMULATE_GPU_FILES") != "1",
+                    reason="hours of emulation; set OSQPMI_EMULATE_GPU_FILES=1")
+@pytest.mark.parametrize("name,select,cus", GPU_FILES)
+def test_gpu_file_on_cpu_kernels(simt_lib, name, select, cus):
+    env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
+               SIMT_WATCHDOG="5000")
+    if cus:
+        env["SIMT_CUS"] = cus
+    args = [sys.executable, os.path.join(SIMT, "pytest_on_simt.py"),
+            os.path.join(ROOT, "tests", name), "-m", "gpu", "-q", "-p", "no:faulthandler"]
+    if select:
+        args += ["-k", select]
+    r = subprocess.run(args, capture_output=True, text=True, env=env, cwd=ROOT, timeout=6 * 3600)
+    print(r.stdout[-3000:])
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    assert " passed" in r.stdout and "failed" not in r.stdout
