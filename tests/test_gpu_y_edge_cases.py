@@ -234,3 +234,21 @@ def test_band_factor_at_its_largest(pm, precision):
     assert info["pcg_iter"] == info["iter"]
     if precision == "fp64":
         assert info["iter"] == ref.iter
+
+
+@pytest.mark.parametrize("linsys", ["pcg", "dense"])
+def test_fp32_overflow_is_reported_unsolved(pm, linsys):
+    """Finite data whose FP32 products overflow: with q = 1e20 and the
+    scaling off, the curvature p'Kp of the first inner step is about 1e40,
+    past FP32's range.  The FP32 path then stops at the first check with
+    "unsolved" (reading 31) instead of reading infinite or NaN residuals as
+    converged.  With Ruiz and cost scaling on, the same QP is solved with the
+    oracle's status and objective."""
+    qp = QP(sp.csr_matrix(np.eye(3)), 1e20 * np.array([1.0, -1.0, 0.5]),
+            sp.csr_matrix(np.eye(3)), -np.ones(3), np.ones(3), name="q = 1e20")
+    x, y, info = pm.solve(qp, precision="fp32", linsys=linsys, scaling_iters=0)
+    assert info["status_name"] == "unsolved", info["status_name"]
+    assert info["iter"] == 25
+    x, y, info = pm.solve(qp, precision="fp32", linsys=linsys)
+    row = gc.compare(qp, x, y, info, oracle.solve(qp))
+    gc.assert_obj_parity([row], f"{qp.name} scaled, linsys {linsys}")
