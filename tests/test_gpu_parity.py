@@ -186,6 +186,30 @@ def test_deterministic_and_alone_equals_mix(pm):
     assert ia["iter"] == im["iter"] and ia["status"] == im["status"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_polish_after_the_whole_grid_team(pm, precision):
+    """A QP large enough for the whole-grid team (Jacobi PCG on every
+    workgroup of a cooperative launch; the graph path refuses such a batch,
+    which shows the team it runs on) is polished afterwards on one
+    workgroup: the oracle's status and objective, and where both polishes
+    are accepted the polished objectives agree to 1e-6."""
+    qp = qpgen.config_instance(1, 0, n=350, m=3500)
+    print(f"grid team + polish {precision}", flush=True)
+    b = pm.Batch([qp], precision=precision, linsys="pcg", polish=1)
+    with pytest.raises(pm.OSQPError) as e:
+        b.solve_graph()
+    assert e.value.code == 13
+    b.solve()
+    x, y, info = b.get(0)
+    b.close()
+    ref = oracle.solve(qp, polish=1)
+    row = gc.compare(qp, x, y, info, ref)
+    gc.assert_obj_parity([row], f"grid team + polish {precision}")
+    print(f"  polish: device {info['polish_status']}, oracle {ref.polish_status}", flush=True)
+    if info["polish_status"] == 1 and ref.polish_status == 1:
+        assert row["obj_err"] <= 1e-6, row["obj_err"]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_lasso_full_size_grid_team(pm, precision):
     """Workload 2 (Lasso, 10000 x 2000 at 5%): one QP on the whole grid."""
