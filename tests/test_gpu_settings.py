@@ -1,0 +1,70 @@
+"""The solver settings on the GPU, against the oracle: on the exact-factor
+paths in FP64 (dense factor, band factor, low-rank form) every ADMM step is
+the direct method's, so for each setting the device must take the oracle's
+iteration count, rho-bar updates and status, and reach its objective to
+FP64 rounding.  A setting the device read differently from the oracle (a
+relaxation, a check period, a step size, a tolerance) shows as another
+iteration count.  The time limit is checked on its own: the oracle's clock
+is not the device's."""
+from __future__ import annotations
+
+import pytest
+
+import oracle
+import qpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_1711_08013_amd as pm
+    assert pm.device_count() > 0, "no HIP device"
+    return pm
+
+
+# one setting changed at a time from the defaults (Section 5.2's rho rule,
+# the relaxation of Algorithm 1, the check period, the step sizes, Ruiz
+# passes, the tolerances, the iteration cap)
+SWEEP = [
+    {}, {"check_every": 1}, {"check_every": 10}, {"alpha": 1.0}, {"alpha": 1.9},
+    {"rho": 0.01}, {"rho": 1.0}, {"sigma": 1e-3}, {"adaptive_rho": 0},
+    {"scaling_iters": 0}, {"scaling_iters": 3}, {"eps_abs": 1e-5, "eps_rel": 1e-5},
+    {"max_iter": 60, "check_every": 7},
+]
+SHORT = [{"alpha": 1.0}, {"check_every": 10}, {"rho": 0.01}, {"adaptive_rho": 0}]
+
+
+def _case(pm, qp, linsys, code, kw):
+    ref = oracle.solve(qp, **kw)
+    x, y, info = pm.solve(qp, precision="fp64", linsys=linsys, **kw)
+    label = f"{qp.name} {linsys} {kw}"
+    print(f"{label}: {info['status_name']} {info['iter']} iterations, "
+          f"{info['rho_updates']} rho updates (oracle {ref.status} {ref.iter})", flush=True)
+    assert info["linsys"] == code, label
+    assert info["status_name"] == ref.status, label
+    assert info["iter"] == ref.iter, label
+    assert info["rho_updates"] == ref.rho_updates, label
+    assert abs(info["obj_val"] - ref.obj_val) <= 1e-9 * max(1.0, abs(ref.obj_val)), label
+
+
+@pytest.mark.parametrize("kw", SWEEP, ids=lambda kw: ",".join(f"{k}={v}" for k, v in kw.items())
+                         or "defaults")
+def test_dense_factor_follows_every_setting(pm, kw):
+    _case(pm, qpgen.config_instance(1, 2), "dense", 2, kw)
+
+
+@pytest.mark.parametrize("kw", SHORT, ids=lambda kw: ",".join(f"{k}={v}" for k, v in kw.items()))
+def test_band_and_lowrank_follow_the_settings(pm, kw):
+    _case(pm, qpgen.mpc(qpgen.rng_for(3, 7), T=12), "band", 4, kw)
+    _case(pm, qpgen.config_instance(4, 2, n_range=(100, 101)), "lowrank", 3, kw)
+
+
+def test_time_limit(pm):
+    """A limit far below one check period stops the solve at the first check
+    with "time_limit_reached"; a generous one changes nothing."""
+    qp = qpgen.config_instance(1, 2)
+    _, _, info = pm.solve(qp, precision="fp64", time_limit=1e-9)
+    assert info["status_name"] == "time_limit_reached" and info["iter"] == 25
+    _, _, info = pm.solve(qp, precision="fp64", time_limit=100.0)
+    assert info["status_name"] == "solved" and info["iter"] == oracle.solve(qp).iter

@@ -8,10 +8,12 @@ workgroup polishes QPs of different shapes in turn), every launch shape
 set_shape accepts, graph replays, the whole-grid team of a cooperative
 launch, the serving loop, degenerate inputs, certificates, the appendix
 problem classes and the parametric updates -- and each result is compared
-with the oracle.  A device-memory access outside its allocation aborts the
-run with the sanitizer's report, and a barrier or cross-lane operation
-that not every thread reaches aborts it with the call sites.  This checks the kernels' logic and indexing, not the
-GPU's timing or its hardware-specific behaviour."""
+with the oracle; the GPU edge-case and settings test files run against the
+same build.  A device-memory access outside its allocation aborts the run
+with the sanitizer's report, and a barrier or cross-lane operation that not
+every thread reaches aborts it with the call sites.  This checks the
+kernels' logic and indexing, not the GPU's timing or its hardware-specific
+behaviour."""
 from __future__ import annotations
 
 import os
@@ -82,24 +84,27 @@ def test_kernels_on_cpu_match_oracle(simt_lib):
         assert got == k, (name, got, k)
 
 
-def test_gpu_edge_case_file_on_cpu_kernels(simt_lib):
-    """The GPU edge-case tests (degenerate inputs against closed forms, the
-    oracle and the solve alone) with the emulated kernels in place of the
-    device."""
+@pytest.mark.parametrize("name,least", [("test_gpu_y_edge_cases.py", 19),
+                                        ("test_gpu_settings.py", 18)])
+def test_gpu_file_runs_on_cpu_kernels(simt_lib, name, least):
+    """Two GPU test files with the emulated kernels in place of the device:
+    the edge cases (degenerate inputs against closed forms, the oracle and
+    the solve alone) and the settings sweep (the oracle's iteration counts on
+    the exact paths)."""
     env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
                SIMT_WATCHDOG="300")
-    r = subprocess.run([sys.executable, os.path.join(SIMT, "pytest_on_simt.py"),
-                        os.path.join(ROOT, "tests", "test_gpu_y_edge_cases.py"), "-m", "gpu", "-q"],
+    path = os.path.join(ROOT, "tests", name)
+    r = subprocess.run([sys.executable, os.path.join(SIMT, "pytest_on_simt.py"), path,
+                        "-m", "gpu", "-q"],
                        capture_output=True, text=True, env=env, cwd=ROOT, timeout=900)
     print(r.stdout[-3000:])
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
     # every GPU test of the file ran and passed (none skipped)
     c = subprocess.run([sys.executable, "-m", "pytest", "--collect-only", "-q", "-m", "gpu",
-                        "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_gpu_y_edge_cases.py")],
+                        "-p", "no:cacheprovider", path],
                        capture_output=True, text=True, cwd=ROOT, timeout=300)
     n = sum(1 for line in c.stdout.splitlines() if "::" in line)
-    assert n >= 13, c.stdout
+    assert n >= least, c.stdout
     assert f"{n} passed" in r.stdout and "skipped" not in r.stdout, r.stdout[-500:]
 
 
