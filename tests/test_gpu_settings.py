@@ -68,3 +68,44 @@ def test_time_limit(pm):
     assert info["status_name"] == "time_limit_reached" and info["iter"] == 25
     _, _, info = pm.solve(qp, precision="fp64", time_limit=100.0)
     assert info["status_name"] == "solved" and info["iter"] == oracle.solve(qp).iter
+
+
+def _infeasible_pair():
+    """A random QP made primal infeasible by one row bounded below by 1 and
+    the same row bounded above by -1; and one made dual infeasible by taking
+    variable 0 out of P and A, giving it q_0 = -1 and only the bound x_0 >= 0
+    (the ray e_0 lowers the objective without end)."""
+    import numpy as np
+    import scipy.sparse as sp
+    from qpgen import QP
+    base = qpgen.random_qp(20, qpgen.rng_for(9, 40))
+    a = np.random.default_rng(3).standard_normal(20)
+    A = sp.vstack([base.A, sp.csr_matrix(a), sp.csr_matrix(a)], format="csr")
+    pinf = QP(base.P, base.q, A, np.concatenate([base.l, [1.0, -np.inf]]),
+              np.concatenate([base.u, [np.inf, -1.0]]), name="primal infeasible")
+    Pd = base.full_P().toarray()
+    Pd[0, :] = 0.0
+    Pd[:, 0] = 0.0
+    Ad = base.A.toarray()
+    Ad[:, 0] = 0.0
+    Ad = np.vstack([Ad, np.eye(20)[:1]])
+    dinf = QP(sp.csr_matrix(np.triu(Pd)), np.concatenate([[-1.0], base.q[1:]]), sp.csr_matrix(Ad),
+              np.concatenate([base.l, [0.0]]), np.concatenate([base.u, [np.inf]]),
+              name="dual infeasible")
+    return pinf, dinf
+
+
+@pytest.mark.parametrize("eps_inf", [1e-4, 1e-6, 1e-2])
+def test_certificates_follow_the_tolerances(pm, eps_inf):
+    """The infeasibility tests of Section 3.4 with their tolerances changed:
+    on the FP64 dense factor each certificate is found at the check where
+    the oracle finds it (the iteration count moves with the tolerance)."""
+    for qp in _infeasible_pair():
+        ref = oracle.solve(qp, eps_pinf=eps_inf, eps_dinf=eps_inf)
+        x, y, info = pm.solve(qp, precision="fp64", linsys="dense", eps_prim_inf=eps_inf,
+                              eps_dual_inf=eps_inf)
+        label = f"{qp.name} eps_inf={eps_inf}"
+        print(f"{label}: {info['status_name']} at {info['iter']} (oracle {ref.status} at "
+              f"{ref.iter})", flush=True)
+        assert info["status_name"] == ref.status == qp.name.replace(" ", "_"), label
+        assert info["iter"] == ref.iter and info["rho_updates"] == ref.rho_updates, label
