@@ -778,11 +778,16 @@ static int polish(const work_qp *w, const orc_settings *s, double *xb, double *z
     resid_t pr;
     residuals(w, s, xp, zp, yp, Ax, Px, Aty, &pr);
     /* reading: accept when both residuals do not exceed the ADMM ones and
-     * the active duals keep their signs */
+     * the duals of the active inequality rows keep their signs.  Section 4
+     * accepts a point that meets the optimality conditions; on a row with
+     * l_i = u_i both bounds are active, so its dual may take either sign and
+     * is not tested (l and u are scaled by the same E_i, so the equality
+     * holds here exactly when it holds on the input) */
     int ok = isfinite(pr.prim_res) && isfinite(pr.dual_res) &&
              pr.prim_res <= admm_res->prim_res && pr.dual_res <= admm_res->dual_res;
     for (int a = 0; a < na && ok; ++a) {
       int i = rows[a];
+      if (w->l[i] == w->u[i]) continue;
       if (yb[i] < 0.0 && yp[i] > 0.0) ok = 0;
       if (yb[i] > 0.0 && yp[i] < 0.0) ok = 0;
     }

@@ -14,8 +14,9 @@
 // S = I + B Delta^-1 B'.  Then the fixed number of iterative-refinement
 // passes of eq. iterative_refinement against the unregularised matrix (eq.
 // kkt_polish), each one more solve with M.  The polished point is accepted
-// when its unscaled residuals do not exceed the ADMM ones and the active
-// duals keep their signs (reading); otherwise the ADMM solution stays.
+// when its unscaled residuals do not exceed the ADMM ones and the duals of
+// the active inequality rows keep their signs (reading; an equality row's
+// dual may take either sign); otherwise the ADMM solution stays.
 #pragma once
 
 #include "dense.h"
@@ -263,8 +264,9 @@ __device__ __forceinline__ void polish_qp(const WGTeam &tm, DenseLDS<double> &s,
       red[2] = fmax(red[2], fabs(ei * ax));
       red[3] = fmax(red[3], fabs(ei * z));
       // sign flag folded in with fmax (a conditional store of the constant
-      // was dropped by hipcc's backend in this loop)
-      const bool flip = (ai < 0.0 && tyi > 0.0) || (ai > 0.0 && tyi < 0.0);
+      // was dropped by hipcc's backend in this loop); a row with l_i = u_i
+      // has both bounds active, so its dual may take either sign
+      const bool flip = !v.iseq[i] && ((ai < 0.0 && tyi > 0.0) || (ai > 0.0 && tyi < 0.0));
       red[8] = fmax(red[8], flip ? 1.0 : 0.0);
     }
   });

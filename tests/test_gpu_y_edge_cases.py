@@ -252,3 +252,22 @@ def test_fp32_overflow_is_reported_unsolved(pm, linsys):
     x, y, info = pm.solve(qp, precision="fp32", linsys=linsys)
     row = gc.compare(qp, x, y, info, oracle.solve(qp))
     gc.assert_obj_parity([row], f"{qp.name} scaled, linsys {linsys}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_polish_with_a_zero_equality_dual(pm, precision):
+    """A degenerate dual: the equality row x_0 = 0 has multiplier 0 at the
+    optimum (the unconstrained minimiser already meets it), so its ADMM and
+    polished duals are rounding-sized with either sign.  An equality row
+    puts no sign condition on its dual (both bounds are active), so the
+    device's FP64 polish is accepted as the oracle's is, at the optimum
+    known by construction."""
+    from tests.test_oracle_pins import _equality_with_zero_dual
+    cases = [_equality_with_zero_dual(seed) for seed in range(24)]
+    b = pm.Batch([qp for qp, _ in cases], precision=precision, polish=1)
+    b.solve()
+    for i, (qp, xs) in enumerate(cases):
+        x, y, info = b.get(i)
+        assert info["status_name"] == "solved" and info["polish_status"] == 1, qp.name
+        assert np.max(np.abs(x - xs)) <= 1e-9 * max(1.0, np.max(np.abs(xs))), qp.name
+    b.close()

@@ -70,6 +70,10 @@ MUTATIONS = {
         "      for (int k = 0; k < N; ++k) t[k] += dt[k];",
         "      for (int k = 0; k < N; ++k) t[k] -= dt[k];",
         [(pins.test_polish_matches_brute_force, {})]),
+    "polish_sign_test_on_equality_rows": (
+        "      if (w->l[i] == w->u[i]) continue;\n",
+        "",
+        [(pins.test_polish_accepts_a_sign_free_equality_dual, {})]),
     "dual_infeasibility_sign": (
         "  if (!(qdx < -w->c * tol)) return 0;",
         "  if (!(qdx > w->c * tol)) return 0;",

@@ -549,6 +549,36 @@ def test_polish_matches_brute_force(oracle_lib):
     assert ok >= 30
 
 
+def _equality_with_zero_dual(seed):
+    """min 1/2 x'Px + q'x with x_0 = 0 and a slack box on the rest, built so
+    that the unconstrained minimiser x* already has x*_0 = 0: x* is the
+    solution and the equality row's dual is exactly 0."""
+    rng = np.random.default_rng(seed)
+    n = 4
+    M = rng.standard_normal((n, n))
+    P = M @ M.T + 0.5 * np.eye(n)
+    xs = rng.standard_normal(n)
+    xs[0] = 0.0
+    l = -5.0 * np.ones(n)
+    u = 5.0 * np.ones(n)
+    l[0] = u[0] = 0.0
+    qp = QP(sp.csr_matrix(np.triu(P)), -P @ xs, sp.csr_matrix(np.eye(n)), l, u, name=f"eq0 {seed}")
+    return qp, xs
+
+
+def test_polish_accepts_a_sign_free_equality_dual(oracle_lib):
+    """Section 4 accepts a polished point that meets the optimality
+    conditions.  Here the equality row's dual is 0 at the optimum, so the
+    ADMM estimate and the polished value are rounding-sized with either
+    sign; a row with l_i = u_i puts no sign condition on its dual, and the
+    polished point, the exact optimum, must be accepted on every instance."""
+    for seed in range(60):
+        qp, xs = _equality_with_zero_dual(seed)
+        r = oracle_lib.solve(qp, polish=1)
+        assert r.status == "solved" and r.polish_status == 1, seed
+        assert np.max(np.abs(r.x - xs)) <= 1e-9 * max(1.0, np.max(np.abs(xs))), seed
+
+
 @pytest.mark.parametrize("cfg,idx,kw", [(1, 2, {}), (3, 2, {}), (4, 1, {"n_range": (100, 300)}),
                                          (0, 0, {})])
 def test_reported_residuals_match_definition(oracle_lib, cfg, idx, kw):

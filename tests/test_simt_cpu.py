@@ -84,8 +84,8 @@ def test_kernels_on_cpu_match_oracle(simt_lib):
         assert got == k, (name, got, k)
 
 
-@pytest.mark.parametrize("name,least", [("test_gpu_y_edge_cases.py", 19),
-                                        ("test_gpu_settings.py", 21)])
+@pytest.mark.parametrize("name,least", [("test_gpu_y_edge_cases.py", 21),
+                                        ("test_gpu_settings.py", 24)])
 def test_gpu_file_runs_on_cpu_kernels(simt_lib, name, least):
     """Two GPU test files with the emulated kernels in place of the device:
     the edge cases (degenerate inputs against closed forms, the oracle and
