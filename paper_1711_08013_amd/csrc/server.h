@@ -304,8 +304,14 @@ void server_loop(osqp_server *sv) {
         if (ks != sv->keymap.end()) {
           Pool &pl = sv->pools[ks->second.pool];
           const bool opens = !repeats.count(ks->second.pool);
-          if (pl.busy || (opens && launches >= kServerMaxLaunches)) { ++it; continue; }
-          if (opens) ++launches;
+          // a pool still re-solving from an earlier round waits; one taken
+          // in this round is marked busy at once, so that making room for a
+          // later request of this round cannot evict it
+          if (opens && (pl.busy || launches >= kServerMaxLaunches)) { ++it; continue; }
+          if (opens) {
+            ++launches;
+            pl.busy = true;
+          }
           repeats[ks->second.pool].push_back({rq, ks->second.idx});
           chosen[rq->key] = 1;
           it = sv->queue.erase(it);
@@ -320,7 +326,6 @@ void server_loop(osqp_server *sv) {
         chosen[rq->key] = 1;
         it = sv->queue.erase(it);
       }
-      for (auto &kv : repeats) sv->pools[kv.first].busy = true;
       if (!firsts.empty()) {
         new_pool = sv->next_pool++;
         for (auto &r : firsts) sv->pending_keys[r->key] = new_pool;

@@ -83,3 +83,42 @@ def assert_obj_parity(rows, label, repolish=None):
         if not ok:
             bad.append((r["qp"].name, r["obj_err"], g_gpu, g_or, g_pol))
     assert not bad, bad
+
+
+def server_pool_kept_while_chosen(pm):
+    """A repeat of an idle resident pool and a fresh QP that needs that
+    pool's memory, admitted in the same round: the pool chosen for the
+    repeat must not be evicted to make the room (the fresh QP waits until
+    the re-solve is done, then the idle pool is evicted).  The budget fits
+    the pool with a small blocker QP but not with the large one.  Returns
+    the (QP, result) pairs and the server's statistics; every result is
+    checked against the oracle here."""
+    import oracle
+    import qpgen
+
+    def alone_bytes(qp, key=0):
+        sv = pm.Server(hbm_budget_bytes=8 << 30, max_slots=8)
+        sv.wait(sv.submit(qp, key=key))
+        b = sv.stats()["peak_bytes"]
+        sv.close()
+        return b
+
+    plant = qpgen.mpc_plant(qpgen.rng_for(5, 77))
+    first = qpgen.mpc(qpgen.rng_for(5, 7000), T=6, plant=plant)
+    repeat = qpgen.mpc(qpgen.rng_for(5, 7001), T=6, plant=plant)
+    blocker = qpgen.random_qp(6, qpgen.rng_for(5, 7100))
+    big = qpgen.random_qp(80, qpgen.rng_for(5, 7200))
+    pb, bb, gb = alone_bytes(first, 9), alone_bytes(blocker), alone_bytes(big)
+    budget = max(pb + bb, gb) + 1024
+    assert pb + gb > budget and pb + bb <= budget, (pb, bb, gb)
+    sv = pm.Server(hbm_budget_bytes=budget, max_slots=16)
+    sv.wait(sv.submit(first, key=9))          # the pool of key 9, then idle
+    tickets = [sv.submit(blocker), sv.submit(repeat, key=9), sv.submit(big)]
+    outs = [sv.wait(t) for t in tickets]
+    stats = sv.stats()
+    sv.close()
+    pairs = list(zip([blocker, repeat, big], outs))
+    rows = [compare(qp, x, y, info, oracle.solve(qp)) for qp, (x, y, info, _) in pairs]
+    assert_obj_parity(rows, "server pool kept while chosen")
+    assert stats["peak_bytes"] <= budget, (stats, budget)
+    return pairs, stats

@@ -230,6 +230,8 @@ def case_server():
         rows.append(gc.compare(qp, x, y, info, oracle.solve(qp)))
     gc.assert_obj_parity(rows, "server")
     yield f"server: {stats['completed']} requests in {stats['batches']} launches"
+    _, st = gc.server_pool_kept_while_chosen(pm)
+    yield f"server: a pool chosen for a repeat is kept under budget pressure ({st['batches']} launches)"
 
 
 def case_edges():

@@ -103,3 +103,13 @@ def test_server_repeated_structure_warm(pm):
     sv.close()
     rows = [gc.compare(q, x, y, info, oracle.solve(q)) for q, (x, y, info, lat) in zip(qps, outs)]
     gc.assert_obj_parity(rows, "server repeats of one plant")
+
+
+def test_server_keeps_a_pool_chosen_for_a_repeat(pm):
+    """Budget pressure in one admission round: a repeat of an idle resident
+    pool and a fresh QP that needs the pool's memory.  The pool is not
+    evicted under the repeat; every request is solved with the oracle's
+    status and objective, within the budget."""
+    pairs, stats = gc.server_pool_kept_while_chosen(pm)
+    assert all(out[2]["status_name"] == "solved" for _, out in pairs)
+    print("pool-reserve stats", stats, flush=True)
