@@ -327,7 +327,9 @@ osqp_int osqp_server_submit(osqp_server *sv, const osqp_problem *p, uint64_t str
                             const osqp_float *x_ws, const osqp_float *y_ws, uint64_t *ticket);
 /* Block until request `ticket` is done; copy x (n), y (m), info and the
  * latency (completion minus submission, seconds).  Any output may be NULL.
- * Returns the request's own error code if its setup or solve failed. */
+ * Returns the request's own error code if its setup or solve failed.  A
+ * ticket is collected once: OSQP_ERR_INDEX for an unknown ticket or one
+ * already collected (also for a second thread waiting on the same one). */
 osqp_int osqp_server_wait(osqp_server *sv, uint64_t ticket, osqp_float *x, osqp_float *y,
                           osqp_info *info, double *latency_s);
 /* Counters: requests completed, micro-batches launched, peak concurrent

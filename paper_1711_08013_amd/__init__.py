@@ -417,6 +417,8 @@ class Server:
         return t.value
 
     def wait(self, ticket: int):
+        if ticket not in self._sizes:   # never issued here, or already collected
+            raise OSQPError(11, "osqp_server_wait")
         n, m = self._sizes[ticket]
         x = np.zeros(n)
         y = np.zeros(max(m, 1))

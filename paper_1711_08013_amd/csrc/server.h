@@ -479,11 +479,16 @@ osqp_int osqp_server_wait(osqp_server *sv, uint64_t ticket, osqp_float *x, osqp_
                           osqp_info *info, double *latency_s) {
   if (!sv) return OSQP_ERR_NOT_SETUP;
   std::unique_lock<std::mutex> lk(sv->mu);
+  if (sv->results.find(ticket) == sv->results.end()) return OSQP_ERR_INDEX;
+  // a ticket is collected once: a second waiter on it finds it gone
+  sv->cv_done.wait(lk, [&] {
+    auto f = sv->results.find(ticket);
+    return f == sv->results.end() || f->second.done;
+  });
   auto it = sv->results.find(ticket);
   if (it == sv->results.end()) return OSQP_ERR_INDEX;
-  sv->cv_done.wait(lk, [&] { return sv->results[ticket].done; });
-  ServerResult r = std::move(sv->results[ticket]);
-  sv->results.erase(ticket);
+  ServerResult r = std::move(it->second);
+  sv->results.erase(it);
   lk.unlock();
   if (r.rc != OSQP_OK) return r.rc;
   if (x) std::memcpy(x, r.x.data(), sizeof(double) * r.x.size());

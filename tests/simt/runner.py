@@ -221,6 +221,9 @@ def case_server():
         tickets = [sv.submit(qp, key=k) for qp, k in reqs]
         outs = [sv.wait(t) for t in tickets]
         stats = sv.stats()
+        # a ticket is collected once (OSQP_ERR_INDEX from the C entry point)
+        rc = pm.lib().osqp_server_wait(sv._h, ctypes.c_uint64(tickets[0]), None, None, None, None)
+        assert rc == 11, rc
     assert stats["completed"] == len(reqs), stats
     # every request: the oracle's status, the eps test and the objective bar
     # (warm re-solves of the pool may stop at another eps-solution; they are

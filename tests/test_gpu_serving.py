@@ -58,6 +58,22 @@ def test_server_results_match_oracle_and_overlap(pm):
     assert stats["batches"] >= 2
 
 
+def test_server_ticket_is_collected_once(pm):
+    """A result is handed out once: waiting again on its ticket (or on one
+    never issued) is OSQP_ERR_INDEX."""
+    sv = pm.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    t = sv.submit(qpgen.random_qp(10, qpgen.rng_for(5, 31)))
+    assert sv.wait(t)[2]["status_name"] == "solved"
+    import ctypes
+    for bad in (t, t + 1000):
+        with pytest.raises(pm.OSQPError) as e:
+            sv.wait(bad)
+        assert e.value.code == 11
+        # the C entry point itself (outputs may be NULL)
+        assert pm.lib().osqp_server_wait(sv._h, ctypes.c_uint64(bad), None, None, None, None) == 11
+    sv.close()
+
+
 def test_server_alone_equals_mix(pm):
     """A fresh request gives bitwise the same result alone and in the mix."""
     target = qpgen.random_qp(60, qpgen.rng_for(5, 4242))
