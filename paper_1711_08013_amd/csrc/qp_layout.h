@@ -23,7 +23,8 @@ struct QPDesc {
                              //   reducing ordering (band)
   int dld;                   // leading dimension of the dense factor / of S;
                              // the block size nb of the band factor
-  int64_t dense_off;         // offset in the dense arena (1, 3) or low-rank arena (2)
+  int64_t dense_off;         // offset in the dense arena (1) or the FP64 low-rank
+                             // arena (2, and 3: the band tiles live there too)
   int64_t mr_off;            // offset of the list of A rows with >= 2 entries
   int mr_cnt;                // length of that list
   int plr;                   // 1: polish through the low-rank (Woodbury) condensed solve
