@@ -191,7 +191,8 @@ def stored_traffic(workload: str, shape):
 # ---------------------------------------------------------------------------
 def host_threads(cap: int = 16) -> int:
     """Host threads for the oracle pool: the CPUs this process may run on,
-    at most `cap` (a one-GPU machine's share of its host)."""
+    at most `cap` (on a shared multi-GPU host, about one GPU's share of its
+    cores)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
