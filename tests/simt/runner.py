@@ -183,13 +183,16 @@ def case_graph():
 
 
 def case_grid():
-    """A QP large enough for the whole-grid team (cooperative launch, grid
-    barriers, two-level reductions), 50 ADMM iterations in both precisions:
-    the same status as the oracle and an objective near its iterate's (the
-    Jacobi inner solves are inexact); the solve graph is refused."""
-    qp = qpgen.config_instance(1, 0, n=400, m=4000)
-    for prec in ("fp64", "fp32"):
-        b = pm.Batch([qp], precision=prec, linsys="pcg", max_iter=50)
+    """QPs large enough for the whole-grid team (cooperative launch, grid
+    barriers, two-level reductions): one whose vectors fit the LDS stage
+    (n = 400, m = 4000; FP64, 50 ADMM iterations) and one too large for any
+    staging, every gather from memory (n = 1000, m = 16000; FP32, 25
+    iterations).  The oracle's status and an objective near its iterate's
+    (the Jacobi inner solves are inexact); the solve graph is refused."""
+    cases = [(qpgen.config_instance(1, 0, n=400, m=4000), "fp64", 50),
+             (qpgen.random_qp(1000, qpgen.rng_for(9, 77), m=16000, density=0.01), "fp32", 25)]
+    for qp, prec, iters in cases:
+        b = pm.Batch([qp], precision=prec, linsys="pcg", max_iter=iters)
         try:
             b.solve_graph()
             raise AssertionError("graph accepted for a whole-grid QP")
@@ -198,12 +201,12 @@ def case_grid():
         b.solve()
         x, y, info = b.get(0)
         b.close()
-        ref = oracle.solve(qp, max_iter=50)
+        ref = oracle.solve(qp, max_iter=iters)
         assert info["status_name"] == ref.status == "max_iter_reached", (info["status_name"], ref.status)
         assert np.isfinite(x).all() and np.isfinite(y).all()
         err = abs(info["obj_val"] - ref.obj_val) / max(1.0, abs(ref.obj_val))
         assert err <= 1e-2, err
-        yield f"grid team {prec}: obj {info['obj_val']:.6f} (oracle {ref.obj_val:.6f})"
+        yield f"grid team {qp.name} {prec}: obj {info['obj_val']:.6f} (oracle {ref.obj_val:.6f})"
 
 
 def case_server():
