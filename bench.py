@@ -285,6 +285,25 @@ def fp64_plain(pm, qps, budget_s: float, extra: dict):
             "p99_latency_ms": float(np.percentile(times, 99) * 1e3)}
 
 
+def high_accuracy_leg(pm, qps, extra, shape):
+    """The same batch at the paper's high-accuracy setting, eps = 1e-5."""
+    hb = pm.Batch(qps, precision="fp32", eps_abs=1e-5, eps_rel=1e-5, max_iter=20000, **extra)
+    try:
+        if shape:
+            hb.set_shape(*shape)
+        hb.reset()
+        t0 = time.perf_counter()
+        hb.solve()
+        hs = time.perf_counter() - t0
+        hinf = [hb.get(i)[2] for i in range(len(qps))]
+    finally:
+        hb.close()
+    hsolved = sum(1 for i in hinf if i["status_name"] == "solved")
+    return {"eps": 1e-5, "solved": hsolved, "qps_per_s": round(hsolved / hs, 2),
+            "batch_ms": round(hs * 1e3, 3),
+            "mean_iter": round(float(np.mean([i["iter"] for i in hinf])), 1)}
+
+
 def parametric_leg(pm):
     """Parametric re-solves (Section 6) on one QP each: a Lasso path of twelve
     lambda values (q updated, iterate kept) against cold solves, and an MPC
@@ -570,32 +589,27 @@ def main():
                                    f"{threads} host threads ({cpu_wall:.1f} s wall)",
                          "nproc": os.cpu_count(), "cpu_model": cpu_model()},
     }
-    if not args.no_baselines:
-        f64 = fp64_plain(pm, qps, args.fp64_budget, extra)
-        out["fp64_plain"] = f64
-        out["speedup_vs_fp64_plain"] = round(value / f64["qps"], 2) if f64["qps"] > 0 else None
     batch.close()
+
+    # the legs beside the metric: a failure in one is recorded in its entry
+    # (with the exception) and the line is still printed
+    def leg(name, fn):
+        print(f"# {name}", file=sys.stderr, flush=True)
+        try:
+            out[name] = fn()
+        except Exception as e:   # noqa: BLE001 -- reported, not hidden
+            print(f"# {name} failed: {e!r}", file=sys.stderr, flush=True)
+            out[name] = {"error": repr(e)}
+
+    if not args.no_baselines:
+        leg("fp64_plain", lambda: fp64_plain(pm, qps, args.fp64_budget, extra))
+        f64 = out["fp64_plain"].get("qps", 0.0)
+        out["speedup_vs_fp64_plain"] = round(value / f64, 2) if f64 > 0 else None
     if not args.no_high_accuracy:
-        # the same batch at the paper's high-accuracy setting, eps = 1e-5
-        print("# high accuracy", file=sys.stderr, flush=True)
-        hb = pm.Batch(qps, precision="fp32", eps_abs=1e-5, eps_rel=1e-5, max_iter=20000, **extra)
-        if shape:
-            hb.set_shape(*shape)
-        hb.reset()
-        t0 = time.perf_counter()
-        hb.solve()
-        hs = time.perf_counter() - t0
-        hinf = [hb.get(i)[2] for i in range(len(qps))]
-        hsolved = sum(1 for i in hinf if i["status_name"] == "solved")
-        out["high_accuracy"] = {"eps": 1e-5, "solved": hsolved, "qps_per_s": round(hsolved / hs, 2),
-                                "batch_ms": round(hs * 1e3, 3),
-                                "mean_iter": round(float(np.mean([i["iter"] for i in hinf])), 1)}
-        hb.close()
+        leg("high_accuracy", lambda: high_accuracy_leg(pm, qps, extra, shape))
     if not args.no_parametric:
-        print("# parametric re-solves", file=sys.stderr, flush=True)
-        out["parametric"] = parametric_leg(pm)
+        leg("parametric", lambda: parametric_leg(pm))
     if not args.no_serving:
-        print("# serving stream", file=sys.stderr, flush=True)
         if args.serving_full:
             cfg = dict(SERVING_FULL)
             cfg["random_pool"] = max(args.serving_pool, 64)
@@ -603,9 +617,14 @@ def main():
             cfg = {"requests": args.serving_requests, "rate": args.serving_rate,
                    "n_max": args.serving_nmax, "warmup_s": args.serving_warmup,
                    "random_pool": args.serving_pool}
-        out["serving"] = serving_leg(pm, cfg["requests"], cfg["rate"], cfg["n_max"],
-                                     cfg["warmup_s"], cfg["random_pool"], args.serving_bisect)
-        out["serving"]["configuration"] = "full" if args.serving_full else "reduced"
+
+        def serving():
+            res = serving_leg(pm, cfg["requests"], cfg["rate"], cfg["n_max"], cfg["warmup_s"],
+                              cfg["random_pool"], args.serving_bisect)
+            res["configuration"] = "full" if args.serving_full else "reduced"
+            return res
+
+        leg("serving", serving)
     print(json.dumps(out), flush=True)
 
 
