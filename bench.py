@@ -106,7 +106,9 @@ def path_bytes(qps, infos, value_bytes=4, check_every=CHECK_EVERY):
                        tiles -> 16 nb n + 8 (3n); no PCG products
       dense path     : PCG iterations e (2a + p) + 4 (2n + m) + vb (5n + 2m) + 16n,
                        applies (ADMM iterations + inner iterations beyond the
-                       first) vb n^2 + 2 vb n
+                       first) vb n^2 + 2 vb n; in FP64 (vb = 8) the factor
+                       gives the direct step: one apply per iteration and
+                       no PCG products
       Jacobi path    : PCG iterations as above, no applies
       check (FP64, every 25 iterations): 12 (2a + p) + 8 (6n + 6m)
       factorisation (1 + rho updates): low-rank 8 (2 R n + R^2) + e a_m;
@@ -130,6 +132,9 @@ def path_bytes(qps, infos, value_bytes=4, check_every=CHECK_EVERY):
             nb = 64
             work = pcg * (16 * nb * n + 8 * 3 * n)
             fact_b = 16 * nb * n + e * (a + p)
+        elif path == 2 and vb == 8:
+            work = pcg * (vb * n * n + 2 * vb * n)
+            fact_b = 3 * vb * n * n
         elif path == 2:
             work = pcg * pcg_b + (it + max(0, pcg - it)) * (vb * n * n + 2 * vb * n)
             fact_b = 3 * vb * n * n

@@ -69,6 +69,11 @@ def test_path_bytes_hand_count():
     applies = (it + (pcg - it)) * (4 * n * n + 8 * n)
     fact = (1 + rho_up) * 3 * 4 * n * n
     assert bench.path_bytes([qp], [info]) == admm + pcg * pcg_b + applies + chk + fact
+    # FP64 dense factor: the direct step, one apply per iteration
+    info64 = {"iter": it, "pcg_iter": it, "rho_updates": rho_up, "linsys": 2}
+    admm64 = it * (12 * (a + p) + 8 * (6 * n + m) + 12 * a + 8 * (3 * n + 9 * m))
+    assert bench.path_bytes([qp], [info64], value_bytes=8) == \
+        admm64 + it * (8 * n * n + 16 * n) + chk + (1 + rho_up) * 3 * 8 * n * n
     # low-rank direct step: one apply per counted inner step, no PCG products
     info["linsys"] = 3
     work = pcg * (e * (am + a) + 8 * (R * R + 4 * n + 2 * m))
