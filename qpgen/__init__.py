@@ -26,7 +26,8 @@ import scipy.sparse as sp
 
 __all__ = [
     "QP", "rng_for", "sparse_normal", "random_qp", "eq_qp", "lasso",
-    "mpc", "portfolio", "huber", "banded", "box_qp", "config_instance", "serving_trace",
+    "mpc", "portfolio", "huber", "banded", "few_dense_rows", "box_qp", "config_instance",
+    "serving_trace",
 ]
 
 
@@ -311,6 +312,20 @@ def banded(rng: np.random.Generator, n: int, w: int, stride: int = 8) -> QP:
     u = np.concatenate([0.5 * np.ones(len(starts)), np.ones(n)])
     q = 2.0 * rng.standard_normal(n)
     return QP(_csr(P), q, _csr(A), l, u, name=f"banded(n={n},w={w})")
+
+
+def few_dense_rows(rng: np.random.Generator, n: int, rows: int = 6, box: float = 2.0) -> QP:
+    """A large QP whose reduced matrix is dense but cheap to factor exactly
+    on the CPU: P tridiagonal (diagonal U[1, 2], off-diagonal U[-0.3, 0.3]),
+    `rows` dense rows of A (entries N(0, 1/n), bounds [-0.1, 0.1]) and a box
+    [-box, box] on every variable; q ~ N(0, 9)."""
+    P = sp.diags([rng.uniform(1.0, 2.0, n), rng.uniform(-0.3, 0.3, n - 1)], [0, 1], format="csr")
+    W = rng.standard_normal((rows, n)) / math.sqrt(n)
+    A = sp.vstack([sp.csr_matrix(W), sp.identity(n)], format="csr")
+    l = np.concatenate([-0.1 * np.ones(rows), -box * np.ones(n)])
+    u = np.concatenate([0.1 * np.ones(rows), box * np.ones(n)])
+    return QP(_csr(P), 3.0 * rng.standard_normal(n), _csr(A), l, u,
+              name=f"few_dense_rows(n={n},rows={rows})")
 
 
 # --------------------------------------------------------------------------

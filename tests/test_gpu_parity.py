@@ -210,6 +210,31 @@ def test_polish_after_the_whole_grid_team(pm, precision):
         assert row["obj_err"] <= 1e-6, row["obj_err"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_path_at_its_limits(pm, precision):
+    """The dense path at its size limits, on QPs the oracle factors cheaply
+    (tridiagonal P, six dense rows of A, a box): n = 3000, the largest QP
+    polished through the dense condensed system (47 diagonal blocks of 64),
+    where the polished point is the oracle's; and n = 4096, the largest QP
+    given the dense factor on request, where polishing is reported as not
+    run.  Both take the oracle's status and objective with one exact step
+    per ADMM iteration."""
+    for n, polish_expected in ((3000, None), (4096, 0)):
+        qp = qpgen.few_dense_rows(np.random.default_rng(11), n)
+        print(f"dense limit n={n} {precision}", flush=True)
+        ref = oracle.solve(qp, polish=1)
+        x, y, info = pm.solve(qp, precision=precision, linsys="dense", polish=1)
+        assert info["linsys"] == 2
+        row = gc.compare(qp, x, y, info, ref)
+        gc.assert_obj_parity([row], f"dense limit n={n} {precision}")
+        assert info["pcg_iter"] == info["iter"]
+        if polish_expected is None:
+            assert info["polish_status"] == ref.polish_status == 1
+            assert np.max(np.abs(x - ref.x)) <= 1e-8 * max(1.0, np.max(np.abs(ref.x)))
+        else:
+            assert info["polish_status"] == polish_expected
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_lasso_full_size_grid_team(pm, precision):
     """Workload 2 (Lasso, 10000 x 2000 at 5%): one QP on the whole grid."""
