@@ -40,7 +40,12 @@ WORKLOADS = {
     "portfolio": (4, 1024, "batched factor-model portfolio, 1024 QPs, n in [100,2000], "
                            "k=n/10, F 50% dense, FP32 with FP64 polish", {"polish": 1}),
     "mpc": (3, 4096, "batched linear MPC, 4096 QPs, nx=20, nu=10, T in [5,20], FP32", {}),
+    "lasso": (2, 1, "Lasso 10000 x 2000 at 5% as one QP (n = m = 14000) on the whole grid, "
+                    "FP32 PCG with FP64 residuals", {}),
 }
+# the kernel whose launch time the roofline divides by
+KERNEL = {"portfolio": "solve_wg_kernel<float>", "mpc": "solve_wg_kernel<float>",
+          "lasso": "solve_grid_kernel<float>"}
 # launch shape (workgroup size : lane divisor) applied before the timed
 # steps: the fastest of the shapes timed earlier on each workload (the same
 # workgroup size the setup picks, so the grid stays the setup's)
@@ -472,6 +477,59 @@ def serving_leg(pm, n_req, rate, n_max, warmup_s, random_pool, bisect_steps):
     return out
 
 
+def workload_leg(pm, name, steps=3, warmup=1, sample=16, threads=16, count=None):
+    """Another workload timed as the main one is (its batch, launch shape,
+    kernel time from the batch's events, the algorithmic byte model), with
+    its own CPU baseline: the oracle on `sample` QPs spread over the batch,
+    whose results are also the reference of the error report."""
+    qps, desc, extra = build_workload(name, count)
+    t0 = time.perf_counter()
+    batch = pm.Batch(qps, precision="fp32", **extra)
+    setup_s = time.perf_counter() - t0
+    try:
+        shape = DEFAULT_SHAPES.get(name)
+        if shape:
+            batch.set_shape(*(int(v) for v in shape.split(":")))
+        for _ in range(warmup):
+            batch.reset()
+            batch.solve()
+        kernel_ms, t0 = [], time.perf_counter()
+        for _ in range(steps):
+            batch.reset()
+            batch.solve()
+            kernel_ms.append(batch.last_kernel_ms())
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        results = [batch.get(i) for i in range(len(qps))]
+    finally:
+        batch.close()
+    infos = [r[2] for r in results]
+    kms = float(np.mean(kernel_ms))
+    algo = algorithmic_bytes(qps, infos)
+    achieved = algo / (kms * 1e-3) / 1e9
+    idx = sorted(set(np.linspace(0, len(qps) - 1, min(sample, len(qps))).astype(int).tolist()))
+    sub = [qps[i] for i in idx]
+    refs, cpu_wall = oracle_pool(sub, extra, min(threads, len(sub)))
+    solved = sum(1 for i in infos if i["status_name"] == "solved")
+    paths = {}
+    for i in infos:
+        paths[LINSYS_NAMES.get(i["linsys"], "?")] = paths.get(LINSYS_NAMES.get(i["linsys"], "?"), 0) + 1
+    return {"workload": desc, "count": len(qps), "steps": steps, "setup_s": round(setup_s, 3),
+            "ms_per_step": round(ms, 3), "solved": solved,
+            "solved_qps_per_s": round(solved / (ms * 1e-3), 2), "linsys": paths,
+            "mean_iter": round(float(np.mean([i["iter"] for i in infos])), 1),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": KERNEL[name], "kernel_ms": round(kms, 3),
+                         "algorithmic_bytes": algo},
+            "error_vs_oracle": error_report(sub, [results[i] for i in idx], refs),
+            "cpu_baseline": {"value": round(sum(r.status == "solved" for r in refs) / cpu_wall, 2),
+                             "unit": "QPs/s", "cores": min(threads, len(sub)), "kind": "oracle",
+                             "sample": f"{len(sub)} of {len(qps)} QPs spread over the batch"}}
+
+
+LINSYS_NAMES = {1: "jacobi_pcg", 2: "dense", 3: "lowrank", 4: "band"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +552,8 @@ def main():
     ap.add_argument("--serving-bisect", type=int, default=0,
                     help="bisection steps for the sustainable rate (0: none)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-side-workloads", action="store_true",
+                    help="skip the other workloads' legs (MPC batch, full-size Lasso)")
     ap.add_argument("--no-parametric", action="store_true")
     ap.add_argument("--no-high-accuracy", action="store_true")
     ap.add_argument("--shape", default=None,
@@ -556,7 +616,7 @@ def main():
     traffic = stored_traffic(args.workload, shape) if args.count is None else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "solve_wg_kernel<float>", "kernel_ms": round(kms, 3),
+                "kernel": KERNEL[args.workload], "kernel_ms": round(kms, 3),
                 "algorithmic_bytes": algo,
                 "path_bytes": pbytes,
                 "path_gbs": round(pbytes / (kms * 1e-3) / 1e9, 1)}
@@ -612,6 +672,15 @@ def main():
         out["speedup_vs_fp64_plain"] = round(value / f64, 2) if f64 > 0 else None
     if not args.no_high_accuracy:
         leg("high_accuracy", lambda: high_accuracy_leg(pm, qps, extra, shape))
+    if not args.no_side_workloads:
+        # the workloads not timed above, each with its own oracle sample
+        others = {}
+        for name in WORKLOADS:
+            if name == args.workload:
+                continue
+            leg(f"workload_{name}", lambda name=name: workload_leg(pm, name, threads=threads))
+            others[name] = out.pop(f"workload_{name}")
+        out["other_workloads"] = others
     if not args.no_parametric:
         leg("parametric", lambda: parametric_leg(pm))
     if not args.no_serving:

@@ -170,3 +170,13 @@ def test_host_threads_capped():
     assert 1 <= bench.host_threads() <= 16
     assert bench.host_threads(cap=2) <= 2
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_every_workload_names_its_kernel():
+    """Each workload the benchmark can time (the main one or a side leg)
+    names the kernel its roofline divides by; the single large QP runs on
+    the whole-grid kernel, the batches on the workgroup kernel."""
+    assert set(bench.KERNEL) == set(bench.WORKLOADS)
+    assert bench.WORKLOADS["lasso"][1] == 1 and bench.KERNEL["lasso"].startswith("solve_grid")
+    for name in ("portfolio", "mpc"):
+        assert bench.KERNEL[name].startswith("solve_wg")
