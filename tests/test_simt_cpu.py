@@ -57,23 +57,45 @@ def simt_lib():
     return asan
 
 
-def test_kernels_on_cpu_match_oracle(simt_lib):
+# GPU test files run against the emulated kernels in the CPU suite, with
+# the least number of tests each must hold
+GPU_FILES_CPU = {"test_gpu_y_edge_cases.py": 21, "test_gpu_settings.py": 24}
+
+
+def _finish(p, timeout):
+    try:
+        out, _ = p.communicate(timeout=timeout)
+    except subprocess.TimeoutExpired:
+        p.kill()
+        out, _ = p.communicate()
+    return p.returncode, out
+
+
+@pytest.fixture(scope="module")
+def emulated_runs(simt_lib):
+    """The runner's case groups and the GPU test files above, all started
+    at once (each is one process on the emulated kernels), then collected:
+    {("runner", group index) | ("file", name): (return code, output)}."""
     env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
                SIMT_WATCHDOG="300")
+    procs = {}
     # the cooperative launch runs its whole grid (one workgroup per CU) side
     # by side: that group runs on an emulated device of three CUs
-    procs = [subprocess.Popen([sys.executable, os.path.join(SIMT, "runner.py"), *g],
-                              stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
-                              env=dict(env, SIMT_CUS="3") if g == ["grid"] else env, cwd=ROOT)
-             for g in GROUPS]
-    outs = []
-    for p in procs:
-        try:
-            out, _ = p.communicate(timeout=900)
-        except subprocess.TimeoutExpired:
-            p.kill()
-            out, _ = p.communicate()
-        outs.append((p.returncode, out))
+    for gi, g in enumerate(GROUPS):
+        procs[("runner", gi)] = subprocess.Popen(
+            [sys.executable, os.path.join(SIMT, "runner.py"), *g], stdout=subprocess.PIPE,
+            stderr=subprocess.STDOUT, text=True,
+            env=dict(env, SIMT_CUS="3") if g == ["grid"] else env, cwd=ROOT)
+    for name in GPU_FILES_CPU:
+        procs[("file", name)] = subprocess.Popen(
+            [sys.executable, os.path.join(SIMT, "pytest_on_simt.py"),
+             os.path.join(ROOT, "tests", name), "-m", "gpu", "-q"],
+            stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, cwd=ROOT)
+    return {k: _finish(p, 900) for k, p in procs.items()}
+
+
+def test_kernels_on_cpu_match_oracle(emulated_runs):
+    outs = [v for k, v in emulated_runs.items() if k[0] == "runner"]
     text = "\n".join(o for _, o in outs)
     print(text)
     for rc, out in outs:
@@ -84,28 +106,23 @@ def test_kernels_on_cpu_match_oracle(simt_lib):
         assert got == k, (name, got, k)
 
 
-@pytest.mark.parametrize("name,least", [("test_gpu_y_edge_cases.py", 21),
-                                        ("test_gpu_settings.py", 24)])
-def test_gpu_file_runs_on_cpu_kernels(simt_lib, name, least):
+@pytest.mark.parametrize("name", sorted(GPU_FILES_CPU))
+def test_gpu_file_runs_on_cpu_kernels(emulated_runs, name):
     """Two GPU test files with the emulated kernels in place of the device:
     the edge cases (degenerate inputs against closed forms, the oracle and
     the solve alone) and the settings sweep (the oracle's iteration counts on
     the exact paths)."""
-    env = dict(os.environ, LD_PRELOAD=simt_lib, ASAN_OPTIONS="detect_leaks=0",
-               SIMT_WATCHDOG="300")
-    path = os.path.join(ROOT, "tests", name)
-    r = subprocess.run([sys.executable, os.path.join(SIMT, "pytest_on_simt.py"), path,
-                        "-m", "gpu", "-q"],
-                       capture_output=True, text=True, env=env, cwd=ROOT, timeout=900)
-    print(r.stdout[-3000:])
-    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    rc, out = emulated_runs[("file", name)]
+    print(out[-3000:])
+    assert rc == 0, out[-6000:]
     # every GPU test of the file ran and passed (none skipped)
+    path = os.path.join(ROOT, "tests", name)
     c = subprocess.run([sys.executable, "-m", "pytest", "--collect-only", "-q", "-m", "gpu",
                         "-p", "no:cacheprovider", path],
                        capture_output=True, text=True, cwd=ROOT, timeout=300)
     n = sum(1 for line in c.stdout.splitlines() if "::" in line)
-    assert n >= least, c.stdout
-    assert f"{n} passed" in r.stdout and "skipped" not in r.stdout, r.stdout[-500:]
+    assert n >= GPU_FILES_CPU[name], c.stdout
+    assert f"{n} passed" in out and "skipped" not in out, out[-500:]
 
 
 # Every GPU test file against the emulated kernels: an hour or more per file,
