@@ -211,6 +211,23 @@ def test_polish_after_the_whole_grid_team(pm, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lowrank_beyond_the_lds_stage(pm, precision):
+    """The low-rank (Woodbury) path on a factor-model portfolio too large for
+    the LDS stage (4000 assets: n = 4400, m = 4401), so every gather of its
+    direct step comes from memory: the oracle's status and objective, one
+    direct step per ADMM iteration, the oracle's iteration count in FP64."""
+    qp = qpgen.portfolio(qpgen.rng_for(4, 4000), n=4000)
+    ref = oracle.solve(qp)
+    x, y, info = pm.solve(qp, precision=precision)
+    assert info["linsys"] == 3
+    row = gc.compare(qp, x, y, info, ref)
+    gc.assert_obj_parity([row], f"{qp.name} {precision}")
+    assert info["pcg_iter"] == info["iter"]
+    if precision == "fp64":
+        assert info["iter"] == ref.iter
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_dense_path_at_its_limits(pm, precision):
     """The dense path at its size limits, on QPs the oracle factors cheaply
     (tridiagonal P, six dense rows of A, a box): n = 3000, the largest QP
