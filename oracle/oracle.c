@@ -242,6 +242,9 @@ int orc_mindeg(int N, const int *Kp, const int *Ki, int *perm) {
 /* ------------------------------------------------------------------------ */
 /* Sparse LDL' (Section 3.1): elimination tree + symbolic counts, then the   */
 /* up-looking numeric factorisation; D^-1 is stored so solves do not divide. */
+/* The method is the published up-looking sparse LDL' of T. Davis (2005),    */
+/* the basis Section 7 names for the paper's own direct solver, written out  */
+/* here from its description.                                                */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
