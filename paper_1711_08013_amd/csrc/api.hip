@@ -106,6 +106,39 @@ int pow2_lanes(double avg, int div) {
 }
 
 // ---------------------------------------------------------------------------
+// reduced-system path eligibility (host)
+// ---------------------------------------------------------------------------
+// Rows of A with two or more entries (the rank-k part of A'RA).
+int count_multi_rows(const osqp_problem &p) {
+  int R = 0;
+  for (int i = 0; i < p.m; ++i) R += p.A.indptr[i + 1] - p.A.indptr[i] >= 2;
+  return R;
+}
+
+// The diagonal-plus-low-rank form applies: P diagonal and few multi-entry
+// rows (R of them), so that K = Delta + B'B with B of R <= n/2 rows; and
+// every column with a nonzero diagonal entry of P or an entry in a
+// single-entry row, so that Delta is bounded away from sigma (a column with
+// neither makes S = I + B Delta^-1 B' as ill-conditioned as 1/sigma).  The
+// polishing step takes the same form for its condensed matrix.
+bool lowrank_fits(const osqp_problem &p, int R) {
+  if (R < 1 || 2 * R > p.n || R > kLowRankMaxR) return false;
+  if ((int64_t)R * ((p.n + 7) & ~7) > kLowRankMaxG) return false;
+  std::vector<char> held(p.n, 0);
+  for (int i = 0; i < p.n; ++i)
+    for (int e = p.P_upper.indptr[i]; e < p.P_upper.indptr[i + 1]; ++e) {
+      if (p.P_upper.indices[e] != i) return false;
+      if (p.P_upper.data[e] != 0.0) held[i] = 1;
+    }
+  for (int i = 0; i < p.m; ++i)
+    if (p.A.indptr[i + 1] - p.A.indptr[i] == 1 && p.A.data[p.A.indptr[i]] != 0.0)
+      held[p.A.indices[p.A.indptr[i]]] = 1;
+  for (int j = 0; j < p.n; ++j)
+    if (!held[j]) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // device allocations: hipMalloc / hipFree unless osqp_set_allocator installed
 // a pair; every handle keeps the pair it was created with, so its frees go
 // where its allocations came from
@@ -738,29 +771,11 @@ int batch_setup_impl(osqp_batch **out, int count, const osqp_problem *probs,
       if (p.A.indptr[i + 1] - p.A.indptr[i] >= 2) b->mrows.push_back(i);
     b->desc[k].mr_cnt = (int)((int64_t)b->mrows.size() - b->desc[k].mr_off);
   }
-  // low-rank eligibility: P diagonal and few multi-entry rows, so that
-  // K = Delta + B'B with B of R <= n/2 rows; and every column with a nonzero
-  // diagonal entry of P or an entry in a single-entry row, so that Delta is
-  // bounded away from sigma (a column with neither makes S = I + B Delta^-1 B'
-  // as ill-conditioned as 1/sigma)
-  // (the polishing step takes the same form for its condensed matrix)
+  // low-rank eligibility (lowrank_fits), for the solve and for polishing
   std::vector<char> lowrank(count, 0);
   for (int k = 0; k < count; ++k) {
     const osqp_problem &p = probs[k];
-    bool pdiag = true;
-    std::vector<char> held(p.n, 0);
-    for (int i = 0; i < p.n && pdiag; ++i)
-      for (int e = p.P_upper.indptr[i]; e < p.P_upper.indptr[i + 1]; ++e) {
-        if (p.P_upper.indices[e] != i) { pdiag = false; break; }
-        if (p.P_upper.data[e] != 0.0) held[i] = 1;
-      }
-    for (int i = 0; i < p.m && pdiag; ++i)
-      if (p.A.indptr[i + 1] - p.A.indptr[i] == 1 && p.A.data[p.A.indptr[i]] != 0.0)
-        held[p.A.indices[p.A.indptr[i]]] = 1;
-    for (int j = 0; j < p.n && pdiag; ++j) pdiag = held[j] != 0;
-    const int R = b->desc[k].mr_cnt;
-    const int64_t g = (int64_t)R * ((p.n + 7) & ~7);
-    const bool fits = pdiag && R >= 1 && 2 * R <= p.n && R <= kLowRankMaxR && g <= kLowRankMaxG;
+    const bool fits = lowrank_fits(p, b->desc[k].mr_cnt);
     b->desc[k].plr = fits ? 1 : 0;
     lowrank[k] = fits && s.linsys != OSQP_LINSYS_PCG && s.linsys != OSQP_LINSYS_DENSE;
   }

@@ -106,14 +106,49 @@ struct InFlight {
   std::vector<int> idx;         // batch index of each request
 };
 
-// HBM a request needs on the device (arena, dense factor, polish workspace).
+// HBM a request needs on the device, an upper bound: the arena, the
+// reduced-system path the setup may give it (the largest of those it is
+// eligible for: the dense factor, the low-rank blocks, the band factor with
+// the largest block) with one workgroup's scratch slot, and the polishing
+// workspace of the form it would be polished in.
 size_t estimate_bytes(const osqp_problem &p, const osqp_settings &s) {
   const double t = s.precision == OSQP_PRECISION_FP64 ? 8.0 : 4.0;
   const double a = p.A.nnz, pu = p.P_upper.nnz, n = p.n, m = p.m;
   double b = a * (4 + 4 + 8 + 8 + 8 + 8 + 2 * t) + 2.0 * pu * (4 + 8 + 8 + t) +
-             n * (12 * 8 + 10 * t) + m * (14 * 8 + 10 * t) + 256.0 * 1024;
-  if (s.linsys != OSQP_LINSYS_PCG && p.n <= kDenseAutoN) b += n * (n + 8) * t + n * m * t;
-  if (s.polish && p.n <= kPolishMaxN) b += n * n * 8 + n * m * 8;
+             n * (12 * 8 + 10 * t) + m * (14 * 8 + 10 * t) +
+             1024.0 * 1024;   // descriptors, work lists, grid partials (up to 2048 blocks)
+  const int R = count_multi_rows(p);
+  const bool lr = lowrank_fits(p, R);
+  const double n8 = (p.n + 7) & ~7;
+  double path = 0.0;
+  if (s.linsys != OSQP_LINSYS_PCG) {
+    // dense: factor (n x n8), inverses of its 64 x 64 diagonal blocks, one
+    // rank-k scratch slot (n x R)
+    const double dense = (n * n8 + (double)((p.n + 63) / 64) * 4096.0 + n * R) * t;
+    if (s.linsys == OSQP_LINSYS_DENSE) {
+      if (p.n <= kDenseMaxN) path = dense;
+    } else {
+      if (p.n <= kDenseAutoN) path = dense;
+      if (lr) {
+        const int ldS = (R + 7) & ~7;
+        const double scratch = std::max<double>((double)R * n8,
+                                                (double)R * ldS + (double)spd_inverse_extra(R));
+        path = std::max(path, 8.0 * ((double)lr_layout(p.n, p.m, R, ldS).total + scratch));
+      }
+      bool short_rows = p.n <= kBandMaxN;
+      for (int i = 0; i < p.m && short_rows; ++i)
+        short_rows = p.A.indptr[i + 1] - p.A.indptr[i] <= kBandMaxNB + 1;
+      if (short_rows) {
+        // tiles 2 ceil(n / nb) nb^2 <= 2 (n nb + nb^2) for nb <= 64, the
+        // residual, one formation scratch slot
+        const double tiles = 2.0 * (n * kBandMaxNB + (double)kBandMaxNB * kBandMaxNB);
+        path = std::max(path, 8.0 * (tiles + n8 + (double)band_scratch(kBandMaxNB)));
+      }
+    }
+  }
+  b += path;
+  if (s.polish && (lr || p.n <= kPolishMaxN))
+    b += 8.0 * ((double)polish_ws_doubles(p.n, p.m, R, lr) + 8.0) + 64.0;
   return (size_t)b;
 }
 

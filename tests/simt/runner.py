@@ -240,6 +240,49 @@ def case_server():
     yield f"server: a pool chosen for a repeat is kept under budget pressure ({st['batches']} launches)"
 
 
+def case_server_estimate():
+    """The server admits a request by an estimate of its device memory, which
+    must bound what the request's batch allocates: a counting allocator
+    installed with osqp_set_allocator records the peak of live bytes while
+    each request is solved alone, for the reduced-system paths the estimate
+    distinguishes (dense, low-rank with low-rank polishing, band below and
+    above n = 2500, Jacobi)."""
+    libc = ctypes.CDLL(None)
+    libc.malloc.restype = ctypes.c_void_p
+    libc.malloc.argtypes = [ctypes.c_size_t]
+    libc.free.argtypes = [ctypes.c_void_p]
+    live, peak = {}, [0]
+
+    def alloc(nbytes):
+        p = libc.malloc(nbytes)
+        live[p] = nbytes
+        peak[0] = max(peak[0], sum(live.values()))
+        return p
+
+    def free(p):
+        del live[p]
+        libc.free(p)
+
+    cases = [(qpgen.random_qp(60, qpgen.rng_for(5, 1)), {}, 2),
+             (qpgen.portfolio(qpgen.rng_for(4, 5), n=200), {"polish": 1}, 3),
+             (qpgen.mpc(qpgen.rng_for(3, 6), T=12), {}, 4),
+             (qpgen.banded(np.random.default_rng(5), 3000, 16), {}, 4),
+             (qpgen.random_qp(60, qpgen.rng_for(5, 2)), {"linsys": "pcg"}, 1)]
+    for qp, settings, path in cases:
+        peak[0] = 0
+        pm.set_allocator(alloc, free)
+        try:
+            with pm.Server(hbm_budget_bytes=64 << 30, max_slots=4, **settings) as sv:
+                x, y, info, _ = sv.wait(sv.submit(qp))
+                est = sv.stats()["peak_bytes"]
+        finally:
+            pm.set_allocator()
+        assert info["linsys"] == path, (qp.name, info["linsys"])
+        assert not live, "an allocation was not returned"
+        assert 0 < peak[0] <= est, (qp.name, peak[0], est)
+        yield f"server estimate {qp.name}: {peak[0] / 1e6:.2f} MB used <= {est / 1e6:.2f} MB"
+
+
 def case_edges():
     """Scalar QP, no constraints, A = I, LP, empty and free rows."""
     e = dict(eps_abs=1e-6, eps_rel=1e-6, max_iter=50000)
@@ -367,7 +410,7 @@ def case_allocator():
 
 
 CASES = {"paths": case_paths, "mpc": case_mpc, "polish": case_polish,
-         "polish_batch": case_polish_batch, "shapes": case_shapes,
+         "polish_batch": case_polish_batch, "server_estimate": case_server_estimate, "shapes": case_shapes,
          "graph": case_graph, "grid": case_grid,
          "server": case_server,
          "edges": case_edges, "certificates": case_certificates, "appendix": case_appendix,

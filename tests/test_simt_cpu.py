@@ -37,12 +37,13 @@ def _load_builder():
 simt_build = _load_builder()
 
 # the runner's cases, split over four processes that run side by side
-GROUPS = [["shapes"], ["grid"], ["graph", "paths", "mpc"],
+GROUPS = [["shapes"], ["grid"], ["graph", "paths", "mpc"], ["server_estimate"],
           ["polish", "polish_batch", "edges", "certificates", "appendix", "updates", "server",
            "allocator"]]
 EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 8, "mpc": 1, "polish": 4, "polish_batch": 2,
                "edges": 6,
-               "certificates": 2, "appendix": 6, "updates": 1, "server": 2, "allocator": 1}
+               "certificates": 2, "appendix": 6, "updates": 1, "server": 2, "allocator": 1,
+               "server_estimate": 5}
 
 
 @pytest.fixture(scope="module")
