@@ -61,6 +61,9 @@ typedef double osqp_float;
                                     /* else Jacobi PCG                         */
 #define OSQP_LINSYS_PCG 1           /* reduced system, Section 3.1 indirect   */
 #define OSQP_LINSYS_DENSE 2         /* dense Cholesky of the reduced matrix   */
+                                    /* (n <= 4096, else Jacobi PCG): the      */
+                                    /* direct step in FP64, the exact PCG     */
+                                    /* preconditioner in FP32                 */
 #define OSQP_LINSYS_LOWRANK 3       /* P diagonal, few multi-entry rows of A:  */
                                     /* Woodbury form of the reduced matrix,    */
                                     /* else as AUTO (the same order as AUTO)   */
@@ -123,12 +126,19 @@ typedef struct {
 typedef struct {
   osqp_int status;         /* OSQP_SOLVED, ...                               */
   osqp_int iter;           /* ADMM iterations                                */
-  osqp_int pcg_iter;       /* total inner PCG iterations                     */
+  osqp_int pcg_iter;       /* total inner PCG iterations (one per ADMM      */
+                           /* iteration where the step is a direct one)     */
   osqp_int rho_updates;
-  osqp_int polish_status;  /* 1 accepted, -1 rejected, 0 not run            */
+  osqp_int polish_status;  /* 1 accepted, -1 rejected, 0 not run; accepted */
+                           /* when the polished residuals are not larger   */
+                           /* than the ADMM ones and the duals of active   */
+                           /* inequality rows keep their signs (Section 4) */
   osqp_int linsys;         /* reduced-system path assigned at setup:         */
                            /* OSQP_LINSYS_PCG (Jacobi), _DENSE, _LOWRANK or  */
-                           /* _BAND                                          */
+                           /* _BAND; a factorisation that meets a pivot     */
+                           /* that is not positive (FP32 rounding) solves   */
+                           /* with Jacobi PCG instead, and is tried again   */
+                           /* at the next rho-bar                           */
   osqp_float obj_val;      /* 1/2 x'Px + q'x on the original data (FP64)    */
   osqp_float prim_res, dual_res, eps_prim, eps_dual; /* unscaled, FP64, Sections 3.4/5.1 */
   osqp_float rho_bar;      /* final rho-bar                                  */
