@@ -137,8 +137,8 @@ typedef struct {
                            /* OSQP_LINSYS_PCG (Jacobi), _DENSE, _LOWRANK or  */
                            /* _BAND; a factorisation that meets a pivot     */
                            /* that is not positive (FP32 rounding) solves   */
-                           /* with Jacobi PCG instead, and is tried again   */
-                           /* at the next rho-bar                           */
+                           /* with Jacobi PCG instead; it is tried again   */
+                           /* when rho-bar changes and at the next solve    */
   osqp_float obj_val;      /* 1/2 x'Px + q'x on the original data (FP64)    */
   osqp_float prim_res, dual_res, eps_prim, eps_dual; /* unscaled, FP64, Sections 3.4/5.1 */
   osqp_float rho_bar;      /* final rho-bar                                  */
