@@ -109,3 +109,24 @@ def test_certificates_follow_the_tolerances(pm, eps_inf):
               f"{ref.iter})", flush=True)
         assert info["status_name"] == ref.status == qp.name.replace(" ", "_"), label
         assert info["iter"] == ref.iter and info["rho_updates"] == ref.rho_updates, label
+
+
+@pytest.mark.parametrize("kw", [{}, {"delta": 1e-8}, {"polish_refine_iter": 0}],
+                         ids=["defaults", "delta=1e-8", "no_refinement"])
+def test_polish_follows_its_settings(pm, kw):
+    """Polishing (Section 4) with its regularisation and its refinement count
+    changed, after the FP64 solve on the dense, low-rank and band paths: the
+    device accepts or rejects the polished point as the oracle does, and an
+    accepted point is the oracle's (x to 1e-8, the objective to 1e-9)."""
+    import numpy as np
+    for qp in (qpgen.config_instance(1, 2), qpgen.config_instance(4, 3, n_range=(100, 101)),
+               qpgen.mpc(qpgen.rng_for(3, 7), T=12)):
+        ref = oracle.solve(qp, polish=1, **kw)
+        x, y, info = pm.solve(qp, precision="fp64", polish=1, **kw)
+        label = f"{qp.name} {kw}"
+        print(f"{label}: polish {info['polish_status']} (oracle {ref.polish_status})", flush=True)
+        assert info["status_name"] == ref.status == "solved", label
+        assert info["polish_status"] == ref.polish_status, label
+        if ref.polish_status == 1:
+            assert np.max(np.abs(x - ref.x)) <= 1e-8 * max(1.0, np.max(np.abs(ref.x))), label
+            assert abs(info["obj_val"] - ref.obj_val) <= 1e-9 * max(1.0, abs(ref.obj_val)), label
