@@ -129,10 +129,12 @@ def test_gpu_file_runs_on_cpu_kernels(emulated_runs, name):
 # Every GPU test file against the emulated kernels: an hour or more per file,
 # so only on request (OSQPMI_EMULATE_GPU_FILES=1).  The cases sized for the
 # device alone (the full-size Lasso, the benchmark's full batches) are left
-# out; the batched file runs on three emulated CUs, where its whole-grid
-# launch is 1,536 fibers instead of 131,072.
+# out; the whole-grid tests (the batched file, polishing after the
+# whole-grid team) run on three emulated CUs, where a whole-grid launch is
+# 1,536 fibers instead of 131,072.
 GPU_FILES = [
-    ("test_gpu_parity.py", "not lasso_full_size", None),
+    ("test_gpu_parity.py", "not lasso_full_size and not whole_grid", None),
+    ("test_gpu_parity.py", "whole_grid", "3"),
     ("test_gpu_batched.py", None, "3"),
     ("test_gpu_parametric.py", None, None),
     ("test_gpu_high_accuracy.py", None, None),
