@@ -646,6 +646,7 @@ def main():
         "batch_latency_ms": round(ms_per_step, 3),
         "statuses": statuses, "setup_s": round(setup_s, 3),
         "launch": {"shape": list(shape) if shape else "setup", "graph": bool(args.graph)},
+        "device": pm.device_info(),
         "roofline": roofline,
         "error_vs_oracle": errors,
         "cpu_baseline": {"value": round(cpu_solved / cpu_wall, 2), "unit": "QPs/s",
