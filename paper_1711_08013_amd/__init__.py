@@ -89,7 +89,8 @@ class _Tuning(ctypes.Structure):
 # free(pointer, ctx)
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
-_allocator_refs = None   # the installed callbacks, kept alive while installed
+_allocator_refs = None   # the installed callbacks
+_allocator_history = []  # every pair installed, kept callable for the process
 
 _lib = None
 
@@ -154,6 +155,9 @@ def set_allocator(alloc=None, free=None):
     refs = (_ALLOC_FN(_a), _FREE_FN(_f))
     _check(lib().osqp_set_allocator(refs[0], refs[1], None), "osqp_set_allocator")
     _allocator_refs = refs
+    # a handle frees through the pair it was created with, also after another
+    # pair (or none) is installed: every pair stays callable for the process
+    _allocator_history.append(refs)
 
 
 def use_torch_allocator(device: int = 0):
