@@ -205,7 +205,11 @@ osqp_int osqp_setup(osqp_solver **out, osqp_int n, osqp_int m,
 
 /* Run ADMM (Algorithm 1, reduced-system PCG form of Section 3.1) until a
  * status of Sections 3.3-3.4 is reached, then unscale (Section 5.1) and,
- * if enabled, polish (Section 4).  Blocks until the result is on the host. */
+ * if enabled, polish (Section 4).  Blocks until the result is on the host.
+ * The first solve starts from zero; each later one starts from the last
+ * iterate and rho-bar (the warm start of Section 6, as after
+ * osqp_update_vectors), unless osqp_warm_start gave another point or
+ * osqp_batch_reset returned the handle to its state after setup. */
 osqp_int osqp_solve(osqp_solver *h);
 
 /* Replace q, l and/or u (NULL = unchanged), unscaled, same sizes
