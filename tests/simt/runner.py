@@ -281,6 +281,19 @@ def case_server_estimate():
         assert not live, "an allocation was not returned"
         assert 0 < peak[0] <= est, (qp.name, peak[0], est)
         yield f"server estimate {qp.name}: {peak[0] / 1e6:.2f} MB used <= {est / 1e6:.2f} MB"
+    # an FP64 server with polishing: fresh QPs and repeats of one key, each
+    # result the polished oracle's status and objective
+    plant = qpgen.mpc_plant(qpgen.rng_for(3, 70))
+    reqs = [(qpgen.random_qp(15, qpgen.rng_for(9, 71)), 0),
+            (qpgen.portfolio(qpgen.rng_for(4, 72), n=150), 0),
+            (qpgen.mpc(qpgen.rng_for(3, 73), T=6, plant=plant), 5),
+            (qpgen.mpc(qpgen.rng_for(3, 74), T=6, plant=plant), 5)]
+    with pm.Server(hbm_budget_bytes=1 << 30, max_slots=8, precision="fp64", polish=1) as sv:
+        outs = [sv.wait(t) for t in [sv.submit(qp, key=k) for qp, k in reqs]]
+    rows = [gc.compare(qp, x, y, info, oracle.solve(qp, polish=1))
+            for (qp, _), (x, y, info, _) in zip(reqs, outs)]
+    gc.assert_obj_parity(rows, "server fp64 polish")
+    yield f"server fp64 with polishing: {len(reqs)} requests"
 
 
 def case_edges():

@@ -43,7 +43,7 @@ GROUPS = [["shapes"], ["grid"], ["graph", "paths", "mpc"], ["server_estimate"],
 EXPECTED_OK = {"shapes": 1, "grid": 2, "graph": 1, "paths": 8, "mpc": 1, "polish": 4, "polish_batch": 2,
                "edges": 6,
                "certificates": 2, "appendix": 6, "updates": 1, "server": 2, "allocator": 1,
-               "server_estimate": 5}
+               "server_estimate": 6}
 
 
 @pytest.fixture(scope="module")
