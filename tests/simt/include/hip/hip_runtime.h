@@ -318,13 +318,43 @@ inline void run_blocks(const std::vector<int> &bids, int nt, int gdim,
   if (nblk > 1 && lds_bytes) lds.assign(nblk, std::vector<char>(lds_bytes, char(0xFF)));
   // sweeps alternate between ascending and descending thread order, so a
   // read that is not ordered after its write by a barrier sees the stale
-  // value in one of the two orders
+  // value in one of the two orders; SIMT_SHUFFLE=<seed> takes a fresh
+  // pseudo-random order each sweep instead (more orderings, reproducible):
+  // the workgroups in a random order, each one's threads in a random order
+  // (a workgroup's threads stay together, so its LDS image is swapped in
+  // once per sweep)
+  static const unsigned long long shuffle_seed = [] {
+    const char *e = std::getenv("SIMT_SHUFFLE");
+    return e ? std::strtoull(e, nullptr, 10) : 0ull;
+  }();
+  static unsigned long long rng = shuffle_seed * 6364136223846793005ull + 1442695040888963407ull;
+  std::vector<int> order;
+  if (shuffle_seed) {
+    order.resize((size_t)total);
+    for (int k = 0; k < total; ++k) order[(size_t)k] = k;
+  }
   bool down = false;
   for (;;) {
     bool ran = false;
     down = !down;
+    if (shuffle_seed) {
+      // Fisher-Yates with a 64-bit LCG, over the workgroups and within each
+      auto pick = [&](int k) {
+        rng = rng * 6364136223846793005ull + 1442695040888963407ull;
+        return (int)((rng >> 33) % (unsigned long long)(k + 1));
+      };
+      std::vector<int> blocks((size_t)nblk);
+      for (int b = 0; b < nblk; ++b) blocks[(size_t)b] = b;
+      for (int k = nblk - 1; k > 0; --k) std::swap(blocks[(size_t)k], blocks[(size_t)pick(k)]);
+      size_t o = 0;
+      for (int b : blocks) {
+        const size_t b0 = o;
+        for (int t = 0; t < nt; ++t) order[o++] = b * nt + t;
+        for (int k = nt - 1; k > 0; --k) std::swap(order[b0 + (size_t)k], order[b0 + (size_t)pick(k)]);
+      }
+    }
     for (int k = 0; k < total; ++k) {
-      const int t = down ? total - 1 - k : k;
+      const int t = shuffle_seed ? order[(size_t)k] : (down ? total - 1 - k : k);
       if (s.f[t].state != RUN) continue;
       ran = true;
       if (!lds.empty() && t / nt != lds_loaded) {
